@@ -1,0 +1,13 @@
+"""Plain FP64 CPU oracle for the unbinned partial-wave-analysis likelihood.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+its Python binding) may import, call or execute anything here; only the test
+suite, the package smoke check and the benchmark's CPU-baseline leg use it.
+It shares no code with the HIP path.
+"""
+
+from .pwa_oracle import (  # noqa: F401
+    Dual, DomainError, new_tag, primal, kallen, kinematics, barrier, legendre,
+    breakup_sq, amplitude, amplitudes, intensity, nll, partials, combine, grad,
+    hvp, hessian, grad_scale, gram, round_to, nll_batched, newton_cg_fit,
+)

@@ -1,0 +1,599 @@
+"""FP64 CPU oracle for the unbinned partial-wave-analysis likelihood, its
+gradient and its Hessian-vector product.
+
+TEST INFRASTRUCTURE ONLY: used by the test suite, the package smoke check and
+the benchmark's CPU-baseline leg; never by the product path.  It shares no
+code with the HIP library.
+
+What is computed (paper Sec. 2.2 and 2.3):
+
+* Intensity, eq. (1): omega(x) = |z(x)|^2 with z = sum_k c_k a_k(x).  The
+  parent here has spin 0, so the helicity sum over mu has a single term, and
+  the overall factor 1/2 is dropped exactly as eq. (3) drops it.
+* Likelihood, eq. (2)-(3), efficiency = 1 (phase-space MC):
+      ln L = sum_{data} ln omega - N_D ln( (1/N_MC) sum_{MC} omega ),
+  and the oracle returns NLL = -ln L.
+* Per-shard sums, eq. (4)-(5): F = sum_data ln omega, G = sum_MC omega, and
+  their first derivatives and Hessian-vector products; eq. (6)-(7) combine
+  them.  Eq. (7) as printed drops the sum over shards on its middle term;
+  `combine` sums it over shards (the only reading consistent with eq. (4)).
+
+Amplitude model (the paper builds covariant-tensor amplitudes, Sec. 2.2; for
+a spin-0 parent decaying to three pseudoscalars the scalar isobar form is used):
+
+    a_k(x) = P_J(cos th) * [F_J(z)/F_J(z0)] / (M^2 - s - i M Gamma(s))
+    Gamma(s) = Gamma * (q/q0)^(2J+1) * (M/sqrt(s)) * [F_J(z)/F_J(z0)]^2
+    z = (q r)^2, z0 = (q0 r)^2, q0 = q(s = M^2), r = 3 GeV^-1,
+    F_0 = 1, F_1 = (1+z)^(-1/2), F_2 = (z^2+3z+9)^(-1/2)   (Blatt-Weisskopf)
+
+Width mode 1 ("constant") sets Gamma(s) = Gamma.
+
+Derivatives: the gradient is the analytic chain rule over the couplings and
+over each amplitude's M and Gamma, the latter obtained exactly by forward-mode
+dual numbers.  The Hessian-vector product is the same gradient code evaluated
+on dual numbers whose tangent is v (forward over the analytic gradient), so
+it carries no truncation error.  All event sums use math.fsum (correctly
+rounded).
+"""
+
+import itertools
+import math
+
+import numpy as np
+
+# Daughter pairs of each channel, 0-based: (a, b, bachelor c).
+#   channel 0 = (12) with c = 3, channel 1 = (13) with c = 2,
+#   channel 2 = (23) with c = 1.
+_PAIRS = ((0, 1, 2), (0, 2, 1), (1, 2, 0))
+
+
+class DomainError(ValueError):
+    """A resonance mass at or below its two-body threshold (q0^2 <= 0)."""
+
+
+# --------------------------------------------------------------------------
+# Forward-mode dual numbers with tags (nested differentiation).
+# --------------------------------------------------------------------------
+_TAGS = itertools.count(1)
+
+
+def new_tag():
+    return next(_TAGS)
+
+
+def _tag(x):
+    return x.t if isinstance(x, Dual) else 0
+
+
+def _parts(x, t):
+    if isinstance(x, Dual) and x.t == t:
+        return x.a, x.b
+    return x, None
+
+
+def _tadd(p, q):
+    if p is None:
+        return q
+    if q is None:
+        return p
+    return p + q
+
+
+def _add(x, y):
+    t = max(_tag(x), _tag(y))
+    xa, xb = _parts(x, t)
+    ya, yb = _parts(y, t)
+    return Dual(xa + ya, _tadd(xb, yb), t)
+
+
+def _mul(x, y):
+    t = max(_tag(x), _tag(y))
+    xa, xb = _parts(x, t)
+    ya, yb = _parts(y, t)
+    tb = None
+    if xb is not None:
+        tb = xb * ya
+    if yb is not None:
+        tb = _tadd(tb, xa * yb)
+    return Dual(xa * ya, tb, t)
+
+
+def _div(x, y):
+    t = max(_tag(x), _tag(y))
+    xa, xb = _parts(x, t)
+    ya, yb = _parts(y, t)
+    q = xa / ya
+    tb = None
+    if xb is not None:
+        tb = xb / ya
+    if yb is not None:
+        tb = _tadd(tb, -(q * yb) / ya)
+    return Dual(q, tb, t)
+
+
+class Dual:
+    """a + b*eps with eps^2 = 0.  Components may be floats, numpy arrays
+    (real or complex) or Duals of a lower tag; the highest tag is outermost."""
+    __array_ufunc__ = None
+    __slots__ = ("a", "b", "t")
+
+    def __init__(self, a, b, t):
+        self.a, self.b, self.t = a, b, t
+
+    def __add__(self, o):
+        return _add(self, o)
+
+    def __radd__(self, o):
+        return _add(o, self)
+
+    def __sub__(self, o):
+        return _add(self, -o)
+
+    def __rsub__(self, o):
+        return _add(o, -self)
+
+    def __neg__(self):
+        return Dual(-self.a, -self.b, self.t)
+
+    def __mul__(self, o):
+        return _mul(self, o)
+
+    def __rmul__(self, o):
+        return _mul(o, self)
+
+    def __truediv__(self, o):
+        return _div(self, o)
+
+    def __rtruediv__(self, o):
+        return _div(o, self)
+
+
+def primal(x):
+    while isinstance(x, Dual):
+        x = x.a
+    return x
+
+
+def dsqrt(x):
+    if isinstance(x, Dual):
+        s = dsqrt(x.a)
+        return Dual(s, x.b / (2.0 * s), x.t)
+    return np.sqrt(x)
+
+
+def dlog(x):
+    if isinstance(x, Dual):
+        return Dual(dlog(x.a), x.b / x.a, x.t)
+    return np.log(x)
+
+
+def dconj(x):
+    if isinstance(x, Dual):
+        return Dual(dconj(x.a), dconj(x.b), x.t)
+    return np.conj(x)
+
+
+def dreal(x):
+    if isinstance(x, Dual):
+        return Dual(dreal(x.a), dreal(x.b), x.t)
+    return np.real(x)
+
+
+def dimag(x):
+    if isinstance(x, Dual):
+        return Dual(dimag(x.a), dimag(x.b), x.t)
+    return np.imag(x)
+
+
+def dabs(x):
+    """Componentwise absolute value (used only for error-scale sums)."""
+    if isinstance(x, Dual):
+        return Dual(dabs(x.a), dabs(x.b), x.t)
+    return np.abs(x)
+
+
+def fsum(x):
+    """Correctly rounded sum of all elements (componentwise for Duals)."""
+    if isinstance(x, Dual):
+        return Dual(fsum(x.a), fsum(x.b), x.t)
+    x = np.asarray(x)
+    if np.iscomplexobj(x):
+        return complex(math.fsum(np.ravel(x.real)), math.fsum(np.ravel(x.imag)))
+    return math.fsum(np.ravel(x))
+
+
+def ipow(x, n):
+    out = x
+    for _ in range(n - 1):
+        out = out * x
+    return out
+
+
+# --------------------------------------------------------------------------
+# Kinematics (two-body breakup momenta and helicity angles).
+# --------------------------------------------------------------------------
+def kallen(x, y, z):
+    """Kallen triangle function lambda(x, y, z)."""
+    return x * x + y * y + z * z - 2.0 * (x * y + x * z + y * z)
+
+
+def breakup_sq(s, ma, mb):
+    """Squared breakup momentum of a two-body system of mass^2 s into (ma, mb)."""
+    return kallen(s, ma * ma, mb * mb) / (4.0 * s)
+
+
+def kinematics(s12, s13, channel, model):
+    """Invariant mass^2 s of the channel's pair (a b), breakup momentum q of
+    a in the (ab) rest frame, and cos of the helicity angle: the angle in the
+    (ab) rest frame between a and the direction opposite to the bachelor c.
+
+    With E_a*, E_c* the energies of a and c in the (ab) frame and p* the
+    bachelor momentum there:
+        s_ac = m_a^2 + m_c^2 + 2 E_a* E_c* + 2 q p* cos(th)."""
+    M = model.parent_mass
+    m = model.masses
+    a, b, c = _PAIRS[channel]
+    ma2, mb2, mc2 = m[a] ** 2, m[b] ** 2, m[c] ** 2
+    s12 = np.asarray(s12, dtype=np.float64)
+    s13 = np.asarray(s13, dtype=np.float64)
+    s23 = M * M + sum(mi * mi for mi in m) - s12 - s13
+    s_ab, s_ac = ((s12, s13), (s13, s12), (s23, s12))[channel]
+    rs = np.sqrt(s_ab)
+    q = np.sqrt(np.maximum(kallen(s_ab, ma2, mb2), 0.0)) / (2.0 * rs)
+    p = np.sqrt(np.maximum(kallen(M * M, s_ab, mc2), 0.0)) / (2.0 * rs)
+    ea = (s_ab + ma2 - mb2) / (2.0 * rs)
+    ec = (M * M - s_ab - mc2) / (2.0 * rs)
+    cos = (s_ac - ma2 - mc2 - 2.0 * ea * ec) / (2.0 * q * p)
+    return s_ab, q, cos
+
+
+def barrier(J, z):
+    """Blatt-Weisskopf damping factor F_J(z), z = (q r)^2."""
+    if J == 0:
+        return 1.0
+    if J == 1:
+        return 1.0 / dsqrt(1.0 + z)
+    if J == 2:
+        return 1.0 / dsqrt(z * z + 3.0 * z + 9.0)
+    raise ValueError("spin must be 0, 1 or 2")
+
+
+def legendre(J, x):
+    if J == 0:
+        return np.ones_like(x)
+    if J == 1:
+        return x
+    if J == 2:
+        return 1.5 * x * x - 0.5
+    raise ValueError("spin must be 0, 1 or 2")
+
+
+def amplitude(kin, channel, J, M, G, model):
+    """a(x) = P_J(cos) (F_J(z)/F_J(z0)) / (M^2 - s - i M Gamma(s)).
+
+    M and G may be dual numbers (for derivatives)."""
+    s, q, cos = kin
+    a, b, _ = _PAIRS[channel]
+    ma, mb = model.masses[a], model.masses[b]
+    r2 = model.r * model.r
+    M2 = M * M
+    q0sq = breakup_sq(M2, ma, mb)
+    if not primal(q0sq) > 0.0:
+        raise DomainError("resonance mass at or below threshold")
+    ratio = barrier(J, q * q * r2) / barrier(J, q0sq * r2)
+    if model.width_mode == 0:
+        gs = G * ipow(q / dsqrt(q0sq), 2 * J + 1) * (M / np.sqrt(s)) * (ratio * ratio)
+    else:
+        gs = G
+    return legendre(J, cos) * ratio / (M2 - s - 1j * (M * gs))
+
+
+def _kin_all(events, model):
+    s12, s13 = events
+    need = sorted(set(model.channel))
+    return {ch: kinematics(s12, s13, ch, model) for ch in need}
+
+
+def amplitudes(events, model, theta):
+    """List of the K amplitude arrays a_k at the events (fixed M, Gamma)."""
+    kin = _kin_all(events, model)
+    out = []
+    for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
+        out.append(amplitude(kin[ch], ch, J, theta[4 * k + 2], theta[4 * k + 3], model))
+    return out
+
+
+def intensity(events, model, theta):
+    """omega(x) = |sum_k c_k a_k(x)|^2 (eq. (1), single helicity term)."""
+    a = amplitudes(events, model, theta)
+    z = 0
+    for k, ak in enumerate(a):
+        z = z + (theta[4 * k] + 1j * theta[4 * k + 1]) * ak
+    return np.abs(z) ** 2
+
+
+# --------------------------------------------------------------------------
+# Event sums F, G and their derivatives (eq. (5) and its derivatives).
+# --------------------------------------------------------------------------
+def _event_sums(events, model, th, is_data, need_grad, abs_terms=False):
+    """Sum over one event set.
+
+    th: list of 4K parameters (floats, or duals carrying a tangent v).
+    Returns S (F for data, G for MC) and, if need_grad, the list of dS/dtheta_p.
+    With abs_terms the per-event terms are replaced by their absolute values
+    (gives the error scale sum |term|, not a derivative)."""
+    kin = _kin_all(events, model)
+    z = 0
+    cols = []
+    for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
+        c = th[4 * k] + 1j * th[4 * k + 1]
+        M, G = th[4 * k + 2], th[4 * k + 3]
+        if need_grad:
+            tm = new_tag()
+            am = amplitude(kin[ch], ch, J, Dual(M, 1.0, tm), G, model)
+            tg = new_tag()
+            ag = amplitude(kin[ch], ch, J, M, Dual(G, 1.0, tg), model)
+            a = am.a
+            # dz/dRe c = a, dz/dIm c = i a, dz/dM = c da/dM, dz/dGamma = c da/dGamma
+            cols += [a, 1j * a, c * am.b, c * ag.b]
+        else:
+            a = amplitude(kin[ch], ch, J, M, G, model)
+        z = z + c * a
+    w = dreal(z) * dreal(z) + dimag(z) * dimag(z)
+    term = dlog(w) if is_data else w
+    S = fsum(dabs(term) if abs_terms else term)
+    grads = []
+    if need_grad:
+        zc = dconj(z)
+        for col in cols:
+            dw = 2.0 * dreal(zc * col)           # d omega / d theta_p
+            t = dw / w if is_data else dw
+            grads.append(fsum(dabs(t) if abs_terms else t))
+    return S, grads
+
+
+def _chunks(events, size):
+    s12, s13 = events
+    n = len(s12)
+    for i in range(0, max(n, 1), size):
+        yield s12[i:i + size], s13[i:i + size]
+
+
+def _sums_chunked(events, model, th, is_data, need_grad, chunk, abs_terms=False):
+    parts = [_event_sums(ev, model, th, is_data, need_grad, abs_terms)
+             for ev in _chunks(events, chunk) if len(ev[0])]
+    if not parts:
+        return 0.0, [0.0] * len(th)
+    S = _dual_fsum([p[0] for p in parts])
+    grads = [_dual_fsum([p[1][j] for p in parts]) for j in range(len(th))] if need_grad else []
+    return S, grads
+
+
+def _dual_fsum(values):
+    if any(isinstance(v, Dual) for v in values):
+        t = max(_tag(v) for v in values)
+        return Dual(_dual_fsum([_parts(v, t)[0] for v in values]),
+                    _dual_fsum([_parts(v, t)[1] or 0.0 for v in values]), t)
+    return math.fsum(values)
+
+
+def partials(data, mc, model, theta, v=None, order=1, chunk=100_000):
+    """Per-shard partial sums of eq. (5) and their derivatives.
+
+    Returns dict with F, G (floats); dF, dG (arrays, order >= 1);
+    HFv, HGv (arrays, when v is given); n_data, n_mc."""
+    theta = np.asarray(theta, dtype=np.float64)
+    P = theta.size
+    need_grad = order >= 1 or v is not None
+    if v is not None:
+        t = new_tag()
+        th = [Dual(float(theta[p]), float(v[p]), t) for p in range(P)]
+    else:
+        th = [float(x) for x in theta]
+    F, dF = _sums_chunked(data, model, th, True, need_grad, chunk)
+    G, dG = _sums_chunked(mc, model, th, False, need_grad, chunk)
+    out = {"n_data": len(data[0]), "n_mc": len(mc[0])}
+    if v is not None:
+        out["F"], out["G"] = F.a, G.a
+        out["dF"] = np.array([g.a for g in dF])
+        out["dG"] = np.array([g.a for g in dG])
+        out["HFv"] = np.array([g.b for g in dF])
+        out["HGv"] = np.array([g.b for g in dG])
+    else:
+        out["F"], out["G"] = F, G
+        if need_grad:
+            out["dF"], out["dG"] = np.array(dF), np.array(dG)
+    return out
+
+
+def combine(parts, n_data=None, n_mc=None, v=None):
+    """Combine per-shard partials with eq. (4), (6) and (7) for NLL = -ln L:
+        NLL   = -sum F_m + N_D ln( sum G_m / N_MC )
+        grad  = -sum dF_m + (N_D / G) sum dG_m
+        H v   = -sum HFv_m + (N_D / G) sum HGv_m - (N_D / G^2) dG (dG . v)
+    with G = sum_m G_m and dG = sum_m dG_m."""
+    if n_data is None:
+        n_data = sum(p["n_data"] for p in parts)
+    if n_mc is None:
+        n_mc = sum(p["n_mc"] for p in parts)
+    F = math.fsum(p["F"] for p in parts)
+    G = math.fsum(p["G"] for p in parts)
+    out = {"nll": -F + n_data * math.log(G / n_mc)}
+    if "dF" in parts[0]:
+        P = parts[0]["dF"].size
+        dF = np.array([math.fsum(p["dF"][j] for p in parts) for j in range(P)])
+        dG = np.array([math.fsum(p["dG"][j] for p in parts) for j in range(P)])
+        out["grad"] = -dF + (n_data / G) * dG
+        if "HFv" in parts[0]:
+            HF = np.array([math.fsum(p["HFv"][j] for p in parts) for j in range(P)])
+            HG = np.array([math.fsum(p["HGv"][j] for p in parts) for j in range(P)])
+            dGv = math.fsum(dG * np.asarray(v))
+            out["hv"] = -HF + (n_data / G) * HG - (n_data / (G * G)) * dG * dGv
+    return out
+
+
+# --------------------------------------------------------------------------
+# Public NLL / gradient / HVP.
+# --------------------------------------------------------------------------
+def _nll_from(th, data, mc, model, need_grad, chunk):
+    F, dF = _sums_chunked(data, model, th, True, need_grad, chunk)
+    G, dG = _sums_chunked(mc, model, th, False, need_grad, chunk)
+    nd, nm = len(data[0]), len(mc[0])
+    val = -F + nd * dlog(G / nm)
+    grads = [-dF[j] + nd * dG[j] / G for j in range(len(dF))]
+    return val, grads
+
+
+def nll(data, mc, model, theta, chunk=100_000):
+    """NLL = -ln L of eq. (3); +inf if a resonance mass is below threshold or
+    the log's argument is not positive."""
+    try:
+        with np.errstate(divide="ignore", invalid="ignore"):
+            val, _ = _nll_from([float(x) for x in theta], data, mc, model, False, chunk)
+    except DomainError:
+        return math.inf
+    return float(val) if np.isfinite(val) else math.inf
+
+
+def grad(data, mc, model, theta, chunk=100_000):
+    """(NLL, gradient of NLL) with the analytic chain rule, eq. (6)."""
+    val, g = _nll_from([float(x) for x in theta], data, mc, model, True, chunk)
+    return float(val), np.array([float(x) for x in g])
+
+
+def hvp(data, mc, model, theta, v, chunk=100_000):
+    """(NLL, gradient, H v): the gradient evaluated on dual numbers whose
+    tangent is v, so the tangent of the gradient is exactly H v."""
+    t = new_tag()
+    th = [Dual(float(theta[p]), float(v[p]), t) for p in range(len(theta))]
+    val, g = _nll_from(th, data, mc, model, True, chunk)
+    return float(val.a), np.array([x.a for x in g]), np.array([x.b for x in g])
+
+
+def hessian(data, mc, model, theta, chunk=100_000):
+    """Full Hessian from P exact Hessian-vector products."""
+    P = len(theta)
+    H = np.empty((P, P))
+    for j in range(P):
+        e = np.zeros(P)
+        e[j] = 1.0
+        H[:, j] = hvp(data, mc, model, theta, e, chunk)[2]
+    return H
+
+
+def grad_scale(data, mc, model, theta, v=None, chunk=100_000):
+    """Absolute-sum error scale of the gradient (and of H v if v is given):
+        S_p = sum_data |d ln omega/d theta_p| + (N_D/G) sum_MC |d omega/d theta_p|.
+    A rounding-error bound for a summed quantity is proportional to it, which
+    makes it the right yardstick where the sum itself cancels (near a minimum)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    P = theta.size
+    if v is not None:
+        t = new_tag()
+        th = [Dual(float(theta[p]), float(v[p]), t) for p in range(P)]
+    else:
+        th = [float(x) for x in theta]
+    _, aF = _sums_chunked(data, model, th, True, True, chunk, abs_terms=True)
+    G, _ = _sums_chunked(mc, model, [primal(x) for x in th], False, False, chunk)
+    _, aG = _sums_chunked(mc, model, th, False, True, chunk, abs_terms=True)
+    nd = len(data[0])
+    if v is None:
+        return np.array([aF[j] + nd / G * aG[j] for j in range(P)])
+    sg = np.array([aF[j].a + nd / G * aG[j].a for j in range(P)])
+    sh = np.array([aF[j].b + nd / G * aG[j].b for j in range(P)])
+    return sg, sh
+
+
+# --------------------------------------------------------------------------
+# Fixed-lineshape (batched) path: Gram matrix and per-start NLL.
+# --------------------------------------------------------------------------
+def gram(events, model, theta, chunk=100_000):
+    """Gm = A^H A with A[j, k] = a_k(x_j): Gm[l, k] = sum_j conj(a_jl) a_jk."""
+    K = len(model.channel)
+    acc = np.zeros((K, K), dtype=complex)
+    parts = []
+    for ev in _chunks(events, chunk):
+        if not len(ev[0]):
+            continue
+        A = np.stack(amplitudes(ev, model, theta), axis=1)
+        parts.append(A.conj().T @ A)
+    if parts:
+        re = np.array([[math.fsum(p[i, j].real for p in parts) for j in range(K)] for i in range(K)])
+        im = np.array([[math.fsum(p[i, j].imag for p in parts) for j in range(K)] for i in range(K)])
+        acc = re + 1j * im
+    return acc
+
+
+def round_to(x, fmt):
+    """Round float64 values to bf16 / fp16 / fp32 (round to nearest even)."""
+    x = np.asarray(x, dtype=np.float64)
+    if fmt == "f64":
+        return x.copy()
+    if fmt == "f32":
+        return x.astype(np.float32).astype(np.float64)
+    if fmt == "f16":
+        return x.astype(np.float16).astype(np.float64)
+    if fmt == "bf16":
+        f = x.astype(np.float32)
+        u = f.view(np.uint32).astype(np.uint64)
+        lsb = (u >> 16) & 1
+        u = ((u + 0x7FFF + lsb) >> 16) << 16
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    raise ValueError(fmt)
+
+
+def nll_batched(data, mc, model, theta, C, fmt="f64", chunk=50_000):
+    """NLL_b = -sum_data ln |(A_D c_b)_i|^2 + N_D ln( c_b^H Gm c_b / N_MC )
+    for every column c_b of the complex K x B matrix C (M, Gamma frozen at
+    theta).  With fmt != 'f64' the operands A and C are first rounded to
+    that format (the contraction itself stays FP64), which isolates the
+    error due to operand rounding."""
+    C = np.asarray(C, dtype=complex)
+    Cr = round_to(C.real, fmt) + 1j * round_to(C.imag, fmt)
+    B = C.shape[1]
+
+    def amat(ev):
+        A = np.stack(amplitudes(ev, model, theta), axis=1)
+        return round_to(A.real, fmt) + 1j * round_to(A.imag, fmt)
+
+    Fp, Gp = [], []
+    for ev in _chunks(data, chunk):
+        if len(ev[0]):
+            Z = amat(ev) @ Cr
+            Fp.append(np.log(Z.real ** 2 + Z.imag ** 2))
+    for ev in _chunks(mc, chunk):
+        if len(ev[0]):
+            Z = amat(ev) @ Cr
+            Gp.append(Z.real ** 2 + Z.imag ** 2)
+    F = np.array([math.fsum(np.concatenate([p[:, b] for p in Fp])) for b in range(B)])
+    G = np.array([math.fsum(np.concatenate([p[:, b] for p in Gp])) for b in range(B)])
+    nd, nm = len(data[0]), len(mc[0])
+    return -F + nd * np.log(G / nm)
+
+
+# --------------------------------------------------------------------------
+# Reference fit: the paper's optimiser (scipy Newton-CG, Sec. 3).
+# --------------------------------------------------------------------------
+def newton_cg_fit(data, mc, model, theta0, xtol=1e-8, maxiter=200, chunk=100_000):
+    """scipy.optimize.minimize(method='Newton-CG') on the oracle's NLL with
+    its analytic gradient and exact Hessian-vector product."""
+    from scipy.optimize import minimize
+
+    cache = {}
+
+    def f(th):
+        key = th.tobytes()
+        if key not in cache:
+            cache.clear()
+            cache[key] = grad(data, mc, model, th, chunk)
+        return cache[key][0]
+
+    def jac(th):
+        f(th)
+        return cache[th.tobytes()][1]
+
+    def hessp(th, p):
+        return hvp(data, mc, model, th, p, chunk)[2]
+
+    return minimize(f, np.asarray(theta0, dtype=np.float64), jac=jac, hessp=hessp,
+                    method="Newton-CG", options={"xtol": xtol, "maxiter": maxiter})

@@ -1,0 +1,127 @@
+"""Workload definitions for the Dalitz-plot likelihood: decay masses,
+resonance layouts and seeded parameter draws.
+
+The paper's own test model (psi(3686) -> phi K+ K-, Table 1 and Sec. 3)
+cannot be rebuilt: its couplings and phases are omitted and its sample is
+not published.  These workloads stand in for it: a spin-0 parent of mass
+1.865 GeV decaying to three distinguishable pseudoscalars (0.494, 0.140,
+0.140 GeV), with K resonances in the three two-body channels.
+
+Parameter vector layout (k-major, four reals per resonance):
+    theta[4k + 0] = Re c_k, theta[4k + 1] = Im c_k,
+    theta[4k + 2] = M_k,    theta[4k + 3] = Gamma_k.
+"""
+
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+PARENT_MASS = 1.865
+DAUGHTER_MASSES = (0.494, 0.140, 0.140)
+R_BARRIER = 3.0  # Blatt-Weisskopf radius, GeV^-1
+
+# Channel c -> (a, b, bachelor) as 0-based daughter indices:
+#   0 = (12) with bachelor 3, 1 = (13) with bachelor 2, 2 = (23) with bachelor 1.
+CHANNEL_PAIRS = ((0, 1, 2), (0, 2, 1), (1, 2, 0))
+
+BASE_SEED = 240309225
+
+# Random streams per workload.
+STREAM_MODEL, STREAM_MC, STREAM_DATA, STREAM_TEST = 0, 1, 2, 3
+
+
+def rng_for(cfg: int, stream: int) -> np.random.Generator:
+    """Seeded generator for workload `cfg` and random stream `stream`."""
+    return np.random.Generator(np.random.PCG64(BASE_SEED + 100 * cfg + stream))
+
+
+def threshold(channel: int) -> float:
+    a, b, _ = CHANNEL_PAIRS[channel]
+    return DAUGHTER_MASSES[a] + DAUGHTER_MASSES[b]
+
+
+def resonance_layout(n_res: int):
+    """Channel and spin of resonance k: channel = k mod 3, J = floor(k/3) mod 3.
+
+    With K >= 9 every (channel, J) pair occurs, which is the largest event
+    stream (3 invariant masses, 6 angular planes, 9 width planes)."""
+    ch = [k % 3 for k in range(n_res)]
+    spin = [(k // 3) % 3 for k in range(n_res)]
+    return ch, spin
+
+
+def draw_theta(channel, spin, rng: np.random.Generator,
+               m_lo=0.6, m_hi=1.6, g_lo=0.03, g_hi=0.3,
+               c_lo=0.2, c_hi=1.0) -> np.ndarray:
+    """Random parameters: M ~ U[m_lo, m_hi] (redrawn while below the channel
+    threshold + 20 MeV), Gamma ~ U[g_lo, g_hi], |c| ~ U(c_lo, c_hi),
+    arg c ~ U(0, 2 pi)."""
+    n = len(channel)
+    th = np.empty(4 * n)
+    for k in range(n):
+        thr = threshold(channel[k]) + 0.02
+        m = rng.uniform(m_lo, m_hi)
+        while m < thr:
+            m = rng.uniform(m_lo, m_hi)
+        g = rng.uniform(g_lo, g_hi)
+        mag = rng.uniform(c_lo, c_hi)
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        th[4 * k:4 * k + 4] = (mag * np.cos(ph), mag * np.sin(ph), m, g)
+    return th
+
+
+@dataclass
+class Workload:
+    """One synthetic workload: model layout, true parameters and sizes."""
+    cfg: int
+    name: str
+    n_res: int
+    channel: List[int]
+    spin: List[int]
+    theta_true: np.ndarray
+    n_data: int
+    n_mc: int
+    width_mode: int = 0          # 0 = mass-dependent width, 1 = constant width
+    parent_mass: float = PARENT_MASS
+    masses: tuple = DAUGHTER_MASSES
+    r: float = R_BARRIER
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_par(self) -> int:
+        return 4 * self.n_res
+
+
+def workload(cfg: int) -> Workload:
+    """The five workloads of the build (0 = CPU-sized fit, 1 = GPU-scale
+    NLL/grad/HVP, 2 = batched fixed-lineshape multi-start, 3 = large
+    differentiation, 4 = learned start)."""
+    if cfg == 0:
+        c2 = 0.6 * np.exp(1.2j)
+        th = np.array([1.0, 0.0, 0.90, 0.10, c2.real, c2.imag, 0.892, 0.05])
+        return Workload(0, "cpu-sized K=2 channel (12), J=0,1", 2, [0, 0], [0, 1],
+                        th, n_data=10_000, n_mc=50_000)
+    if cfg in (1, 4):
+        ch, sp = resonance_layout(12)
+        th = draw_theta(ch, sp, rng_for(cfg, STREAM_MODEL))
+        if cfg == 1:
+            return Workload(1, "gpu-scale K=12, 1M data / 5M MC", 12, ch, sp, th,
+                            n_data=1_000_000, n_mc=5_000_000)
+        return Workload(4, "learned-start K=12 toys", 12, ch, sp, th,
+                        n_data=50_000, n_mc=500_000,
+                        extra={"n_train_toys": 20_000, "n_eval_toys": 200,
+                               "eval_n_data": 1_000_000, "eval_n_mc": 5_000_000,
+                               "n_random_starts": 256, "hist_bins": 32})
+    if cfg == 2:
+        ch, sp = resonance_layout(20)
+        th = draw_theta(ch, sp, rng_for(2, STREAM_MODEL))
+        return Workload(2, "batched fixed-lineshape K=20, 2M data / 10M MC, B=256",
+                        20, ch, sp, th, n_data=2_000_000, n_mc=10_000_000,
+                        extra={"n_starts": 256})
+    if cfg == 3:
+        ch, sp = resonance_layout(30)
+        th = draw_theta(ch, sp, rng_for(3, STREAM_MODEL))
+        return Workload(3, "differentiation K=30, 4M data / 20M MC", 30, ch, sp, th,
+                        n_data=4_000_000, n_mc=20_000_000)
+    raise ValueError(f"unknown workload {cfg}")
