@@ -1,0 +1,239 @@
+/*
+ * pwa.h -- C ABI of the MI355X partial-wave-analysis likelihood library.
+ *
+ * The library evaluates the unbinned negative log-likelihood of a
+ * three-body Dalitz-plot model, its gradient and its Hessian-vector product
+ * (arXiv:2403.09225, Sec. 2.2 eq. (1)-(3) and Sec. 2.3 eq. (4)-(7)), and
+ * drives a Newton-conjugate-gradient fit with them (Sec. 3, the
+ * "NTCG+AutoDiff" method).  Every step of the evaluation runs in HIP kernels
+ * written for gfx950.
+ *
+ * Conventions for every entry point:
+ *   - Plain C: no C++ types or exceptions cross this boundary.
+ *   - Array arguments named d_* are DEVICE pointers; everything else
+ *     (pwa_model, pwa_fit_opts, pwa_fit_report) lives in host memory.
+ *   - The caller owns all device memory.  The library never allocates device
+ *     memory; the workspace is the caller's buffer of pwa_workspace_bytes().
+ *   - Calls taking a hipStream_t only enqueue work on that stream and return
+ *     at once (the exception is pwa_fit, which synchronises).  Outputs are
+ *     valid once the stream reaches the enqueued work.
+ *   - A context is not thread-safe; several contexts may coexist.
+ *   - Return value: PWA_OK (0) or a negative pwa_status.  Arguments are
+ *     validated on the host before any HIP call, so bad arguments are
+ *     reported without touching the device.
+ *
+ * Physics conventions (the paper is silent on them; these are the readings):
+ *   - Parent of spin 0 decaying to three distinguishable pseudoscalars with
+ *     masses m[0..2]; an event is x = (s12, s13), s_ij = (p_i + p_j)^2 in
+ *     GeV^2; s23 = M^2 + sum m_i^2 - s12 - s13.
+ *   - Channel c: 0 = (12) with bachelor 3, 1 = (13) with bachelor 2,
+ *     2 = (23) with bachelor 1.  The helicity angle of channel (ab) is the
+ *     angle, in the (ab) rest frame, between a and the direction opposite to
+ *     the bachelor.
+ *   - Amplitude of resonance k (channel c, spin J in {0,1,2}):
+ *       a_k = P_J(cos th) [F_J(z)/F_J(z0)] / (M_k^2 - s - i M_k Gamma_k(s)),
+ *       Gamma_k(s) = Gamma_k (q/q0)^(2J+1) (M_k/sqrt s) [F_J(z)/F_J(z0)]^2,
+ *     with q the breakup momentum, q0 = q(s = M_k^2), z = (q r)^2, and
+ *     Blatt-Weisskopf F_0 = 1, F_1 = (1+z)^-1/2, F_2 = (z^2+3z+9)^-1/2.
+ *     PWA_WIDTH_CONSTANT sets Gamma_k(s) = Gamma_k.
+ *   - Intensity (eq. (1), one helicity term): w(x) = |sum_k c_k a_k(x)|^2.
+ *   - NLL = -ln L = -sum_data ln w + N_D ln( (1/N_MC) sum_MC w )  (eq. (3)).
+ *   - Parameter vector theta (P = 4K doubles), k-major:
+ *       theta[4k+0] = Re c_k, theta[4k+1] = Im c_k,
+ *       theta[4k+2] = M_k,    theta[4k+3] = Gamma_k.
+ *   - A resonance mass at or below its pair threshold, or a non-positive
+ *     intensity sum, is not an error: the NLL is +inf and a device status
+ *     bit is set (read it with pwa_device_status).
+ */
+#ifndef PWA_H
+#define PWA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PWA_MAX_RES 64
+
+typedef enum pwa_status {
+  PWA_OK = 0,
+  PWA_E_INVALID = -1,   /* null pointer, bad size, bad channel/spin, ...     */
+  PWA_E_WORKSPACE = -2, /* workspace missing, too small or misaligned        */
+  PWA_E_HIP = -3,       /* a HIP runtime call failed (e.g. no device)        */
+  PWA_E_DOMAIN = -4,    /* fit start point outside the model's domain        */
+  PWA_E_NOCONV = -5,    /* fit stopped without meeting xtol; theta = best    */
+  PWA_E_STATE = -6      /* context not bound to events yet                   */
+} pwa_status;
+
+/* Arithmetic of the per-event evaluation.  Event sums are always FP64. */
+typedef enum pwa_precision {
+  PWA_PREC_F64 = 0, /* FP64 event stream and FP64 per-event arithmetic       */
+  PWA_PREC_F32 = 1  /* FP32 event stream and arithmetic, FP64 accumulation   */
+} pwa_precision;
+
+/* Which event streams pwa_bind materialises (bit mask). */
+#define PWA_STREAM_F64 1
+#define PWA_STREAM_F32 2
+
+typedef enum pwa_width_mode {
+  PWA_WIDTH_MASS_DEPENDENT = 0,
+  PWA_WIDTH_CONSTANT = 1
+} pwa_width_mode;
+
+/* Model description (host memory, copied by pwa_create). */
+typedef struct pwa_model {
+  double parent_mass;          /* GeV                                          */
+  double masses[3];            /* daughter masses m1, m2, m3 (GeV)             */
+  double r;                    /* Blatt-Weisskopf radius (GeV^-1)              */
+  int32_t n_res;               /* K, 1 <= K <= PWA_MAX_RES                      */
+  int32_t width_mode;          /* pwa_width_mode                               */
+  int32_t channel[PWA_MAX_RES];/* channel of resonance k: 0, 1 or 2            */
+  int32_t spin[PWA_MAX_RES];   /* spin J of resonance k: 0, 1 or 2             */
+} pwa_model;
+
+typedef struct pwa_ctx pwa_ctx;
+
+/* Create a context for `model` (host memory, copied).
+ * streams: PWA_STREAM_F64 and/or PWA_STREAM_F32 -- the event streams pwa_bind
+ * will build (both are needed for mixed-precision fits).
+ * Errors: PWA_E_INVALID for a null pointer, K out of range, a channel or spin
+ * out of range, non-positive masses, r <= 0, an empty stream mask, or a
+ * parent mass not above the sum of the daughter masses. */
+int pwa_create(const pwa_model* model, int32_t streams, pwa_ctx** out);
+
+/* Destroy a context (null is accepted).  Owns no device memory. */
+void pwa_destroy(pwa_ctx* ctx);
+
+/* Device workspace (bytes) needed to bind n_data data and n_mc MC events:
+ * the parameter-free event stream (the paper's precomputed U, Sec. 2.2:
+ * per channel s, per (channel, J) the width factor and, for J >= 1, the
+ * angular factor, for each event), the resonance table, the per-block
+ * partial sums and the status words.  0 on invalid arguments. */
+size_t pwa_workspace_bytes(const pwa_ctx* ctx, int64_t n_data, int64_t n_mc);
+
+/* Bind events and build the parameter-free event stream in the workspace
+ * (Sec. 2.2: the parameter-free factors are computed once and kept on the
+ * GPU).  d_s12/d_s13: n_data data events; d_mc_s12/d_mc_s13: n_mc MC events
+ * (phase-space distributed, efficiency 1); FP64, contiguous.  The event
+ * arrays are read on `stream` during this call and not retained.
+ * d_ws: caller-owned device buffer of ws_bytes >= pwa_workspace_bytes(),
+ * 256-byte aligned; it must stay allocated while the context is used.
+ * n_data >= 0, n_mc >= 1.
+ * Errors: PWA_E_INVALID (null pointers, sizes), PWA_E_WORKSPACE, PWA_E_HIP. */
+int pwa_bind(pwa_ctx* ctx, const double* d_s12, const double* d_s13, int64_t n_data,
+             const double* d_mc_s12, const double* d_mc_s13, int64_t n_mc,
+             void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Precision of subsequent pwa_nll/pwa_grad/pwa_hvp/pwa_partials calls.
+ * PWA_E_INVALID if that stream was not requested at pwa_create. */
+int pwa_set_precision(pwa_ctx* ctx, int32_t precision);
+
+/* NLL(theta) of eq. (3).  d_theta: P = 4K doubles; d_nll: 1 double. */
+int pwa_nll(pwa_ctx* ctx, const double* d_theta, double* d_nll, hipStream_t stream);
+
+/* NLL and its gradient (eq. (6) with NLL = -ln L) in one pass over the
+ * events.  d_grad: P doubles. */
+int pwa_grad(pwa_ctx* ctx, const double* d_theta, double* d_nll, double* d_grad,
+             hipStream_t stream);
+
+/* Hessian-vector product H v of the NLL (eq. (7) with NLL = -ln L, the
+ * middle term summed over shards), with NLL and gradient from the same pass
+ * (forward-over-reverse: one pass over the events, nothing stored per
+ * event).  d_v, d_hv: P doubles; d_nll and d_grad may be null. */
+int pwa_hvp(pwa_ctx* ctx, const double* d_theta, const double* d_v, double* d_hv,
+            double* d_nll, double* d_grad, hipStream_t stream);
+
+/* Un-combined per-shard sums of eq. (5) and their derivatives for the bound
+ * events (one GPU's share in the paper's multi-GPU scheme, Sec. 2.3).
+ * d_part receives 2*(2+4P) doubles: (hi, lo) double-double pairs of
+ *   [F, G, dF/dtheta (P), dG/dtheta (P), H_F v (P), H_G v (P)]
+ * with F = sum_data ln w, G = sum_MC w.  With d_v null the H v entries are
+ * written as zero. */
+int pwa_partials(pwa_ctx* ctx, const double* d_theta, const double* d_v, double* d_part,
+                 hipStream_t stream);
+
+/* Combine n_shards partial vectors (layout of pwa_partials, consecutive in
+ * d_parts) with eq. (4), (6), (7): NLL, gradient and (if d_hv is non-null)
+ * H v.  The shards are summed in index order in double-double arithmetic,
+ * so the result does not depend on how events were split beyond rounding.
+ * n_data_total, n_mc_total: event counts over all shards.  d_v is needed
+ * when d_hv is non-null. */
+int pwa_combine(int32_t n_par, int32_t n_shards, const double* d_parts,
+                int64_t n_data_total, int64_t n_mc_total, const double* d_v,
+                double* d_nll, double* d_grad, double* d_hv, hipStream_t stream);
+
+/* Newton-CG fit options (host memory). */
+typedef struct pwa_fit_opts {
+  double xtol;            /* stop when mean |step| <= xtol (scipy's rule)      */
+  int32_t maxiter;        /* outer Newton iterations (<= 0: 200)              */
+  int32_t cg_maxiter;     /* CG iterations per Newton step (<= 0: 2P)          */
+  double time_cap_s;      /* wall-clock cap, seconds (<= 0: none); Sec. 3 uses 500 */
+  int32_t hvp_precision;  /* pwa_precision of the HVPs inside CG              */
+  int32_t free_mask_set;  /* 0: all parameters free; 1: use free_mask         */
+  uint8_t free_mask[4 * PWA_MAX_RES]; /* 1 = free, 0 = fixed                   */
+} pwa_fit_opts;
+
+/* Fit report (host memory, written by pwa_fit). */
+typedef struct pwa_fit_report {
+  double nll;             /* NLL at the returned theta                         */
+  double grad_max;        /* max |gradient| over free parameters               */
+  double seconds;         /* wall time of the fit                              */
+  int32_t iterations;     /* Newton iterations                                  */
+  int32_t n_nll;          /* NLL-only evaluations (line search)                */
+  int32_t n_grad;         /* NLL+gradient evaluations                          */
+  int32_t n_hvp;          /* Hessian-vector products                           */
+  int32_t status;         /* pwa_status of the fit                             */
+  int32_t converged;      /* 1 if the xtol test was met                        */
+} pwa_fit_report;
+
+/* Minimise the NLL from d_theta_inout with line-search Newton-CG (truncated
+ * CG on H p = -g using pwa_hvp, strong-Wolfe line search on the FP64 NLL and
+ * gradient) and write the best point back.  The paper fits with scipy's
+ * Newton-CG (Sec. 3); the xtol test follows scipy's (mean absolute step).
+ * Synchronous: returns when the fit ends.  h_rep may be null.
+ * Errors: PWA_E_STATE (unbound), PWA_E_INVALID (options), PWA_E_DOMAIN (NLL
+ * not finite at the start), PWA_E_NOCONV (maxiter/time cap/line-search
+ * failure; theta holds the best point), PWA_E_HIP. */
+int pwa_fit(pwa_ctx* ctx, double* d_theta_inout, const pwa_fit_opts* h_opts,
+            pwa_fit_report* h_rep, hipStream_t stream);
+
+/* Reads and clears the context's sticky device status word (synchronises
+ * the stream).  Bits: 1 = a resonance mass at or below threshold was seen,
+ * 2 = a non-finite NLL was produced.  Negative on error. */
+int pwa_device_status(pwa_ctx* ctx, hipStream_t stream);
+
+/* Static description of a status code. */
+const char* pwa_status_str(int status);
+
+/* Number of parameters P = 4K of a context (or -1 for null). */
+int32_t pwa_n_par(const pwa_ctx* ctx);
+
+/* Kernel launch shape of the NLL/gradient/HVP kernels: `lanes_per_event`
+ * lanes cooperate on one event, each owning `res_per_lane` resonances
+ * (lanes_per_event * res_per_lane >= K).  0, 0 restores the automatic choice.
+ * PWA_E_INVALID for a shape that is not built. */
+int pwa_set_launch_shape(pwa_ctx* ctx, int32_t lanes_per_event, int32_t res_per_lane);
+
+/* Number of thread blocks the NLL/gradient/HVP kernels launch (after
+ * pwa_bind), or -1. */
+int32_t pwa_grid_blocks(const pwa_ctx* ctx);
+
+/* Kernel timing for measurement: while enabled (enable != 0), every
+ * evaluation records a pair of HIP events on the caller's stream around its
+ * per-event pass kernel (the dominant kernel; not the table or finaliser
+ * launches).  pwa_kernel_time synchronises on the last recorded event,
+ * returns the summed duration (ms) and the number of timed launches since
+ * the previous call, and resets them.  Events are created by the library on
+ * first use (no device memory is allocated).  Errors: PWA_E_INVALID,
+ * PWA_E_HIP. */
+int pwa_set_kernel_timing(pwa_ctx* ctx, int32_t enable);
+int pwa_kernel_time(pwa_ctx* ctx, double* total_ms, int64_t* n_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWA_H */

@@ -1,0 +1,200 @@
+"""Python binding of the PWA likelihood library: argument marshalling only.
+
+torch provides device memory and the stream; every step of the evaluation
+runs in the library's HIP kernels.
+
+    lik = Likelihood(channel=[0, 0], spin=[0, 1])
+    lik.bind(data_s12, data_s13, mc_s12, mc_s13)      # tensors or arrays
+    nll = lik.nll(theta)                              # theta: float64 (4K,)
+    nll, g = lik.grad(theta)
+    hv, nll, g = lik.hvp(theta, v)
+    theta_fit, report = lik.fit(theta0, xtol=1e-8)
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PARENT_MASS = 1.865
+DAUGHTER_MASSES = (0.494, 0.140, 0.140)
+R_BARRIER = 3.0
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev_f64(x, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64), device=device)
+
+
+class Likelihood:
+    """Unbinned PWA NLL, gradient and Hessian-vector product on one GPU."""
+
+    def __init__(self, channel, spin, parent_mass=PARENT_MASS, masses=DAUGHTER_MASSES,
+                 r=R_BARRIER, width_mode=0, streams=("f64",), device="cuda"):
+        self.lib = L.load()
+        m = L.PwaModel()
+        m.parent_mass = parent_mass
+        for i in range(3):
+            m.masses[i] = masses[i]
+        m.r = r
+        m.n_res = len(channel)
+        m.width_mode = width_mode
+        if len(channel) > L.PWA_MAX_RES or len(spin) != len(channel):
+            raise ValueError("channel/spin lists must have equal length <= 64")
+        for k, (c, j) in enumerate(zip(channel, spin)):
+            m.channel[k] = int(c)
+            m.spin[k] = int(j)
+        mask = (L.PWA_STREAM_F64 if "f64" in streams else 0) | (L.PWA_STREAM_F32 if "f32" in streams else 0)
+        h = ctypes.c_void_p()
+        L.check("pwa_create", self.lib.pwa_create(ctypes.byref(m), mask, ctypes.byref(h)))
+        self._h = h
+        self.n_res = len(channel)
+        self.n_par = 4 * self.n_res
+        self.device = torch.device(device)
+        self.streams = tuple(streams)
+        self._ws = None
+        self.n_data = self.n_mc = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.pwa_destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------------- binding
+    def workspace_bytes(self, n_data, n_mc):
+        return int(self.lib.pwa_workspace_bytes(self._h, int(n_data), int(n_mc)))
+
+    def bind(self, data_s12, data_s13, mc_s12, mc_s13):
+        """Copy events to the device (if needed) and build the event stream."""
+        d12, d13 = _dev_f64(data_s12, self.device), _dev_f64(data_s13, self.device)
+        m12, m13 = _dev_f64(mc_s12, self.device), _dev_f64(mc_s13, self.device)
+        nd, nm = int(d12.numel()), int(m12.numel())
+        nbytes = self.workspace_bytes(nd, nm)
+        if nbytes == 0:
+            raise ValueError("invalid event counts")
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self._ws = ws
+        wptr = ctypes.c_void_p(ws.data_ptr() + off)
+        L.check("pwa_bind", self.lib.pwa_bind(
+            self._h, _ptr(d12) if nd else None, _ptr(d13) if nd else None, nd,
+            _ptr(m12), _ptr(m13), nm, wptr, nbytes, _stream()))
+        torch.cuda.current_stream().synchronize()  # event arrays may be freed now
+        self.n_data, self.n_mc = nd, nm
+        return self
+
+    def set_precision(self, prec):
+        L.check("pwa_set_precision", self.lib.pwa_set_precision(
+            self._h, L.PWA_PREC_F32 if prec == "f32" else L.PWA_PREC_F64))
+
+    def set_launch_shape(self, lanes_per_event=0, res_per_lane=0):
+        L.check("pwa_set_launch_shape",
+                self.lib.pwa_set_launch_shape(self._h, lanes_per_event, res_per_lane))
+
+    def grid_blocks(self):
+        return int(self.lib.pwa_grid_blocks(self._h))
+
+    def set_kernel_timing(self, enable=True):
+        L.check("pwa_set_kernel_timing", self.lib.pwa_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_time(self):
+        """(summed ms, launches) of the per-event pass kernel since the last call."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        L.check("pwa_kernel_time", self.lib.pwa_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    # ------------------------------------------------------------ evaluation
+    def _theta(self, theta):
+        t = _dev_f64(theta, self.device)
+        if t.numel() != self.n_par:
+            raise ValueError(f"theta must have {self.n_par} entries")
+        return t
+
+    def nll(self, theta):
+        t = self._theta(theta)
+        out = torch.empty((), dtype=torch.float64, device=self.device)
+        L.check("pwa_nll", self.lib.pwa_nll(self._h, _ptr(t), _ptr(out), _stream()))
+        return out
+
+    def grad(self, theta):
+        t = self._theta(theta)
+        out = torch.empty(1 + self.n_par, dtype=torch.float64, device=self.device)
+        L.check("pwa_grad", self.lib.pwa_grad(
+            self._h, _ptr(t), _ptr(out), ctypes.c_void_p(out.data_ptr() + 8), _stream()))
+        return out[0], out[1:]
+
+    def hvp(self, theta, v):
+        t = self._theta(theta)
+        vv = self._theta(v)
+        out = torch.empty(1 + 2 * self.n_par, dtype=torch.float64, device=self.device)
+        base = out.data_ptr()
+        L.check("pwa_hvp", self.lib.pwa_hvp(
+            self._h, _ptr(t), _ptr(vv), ctypes.c_void_p(base + 8 * (1 + self.n_par)),
+            ctypes.c_void_p(base), ctypes.c_void_p(base + 8), _stream()))
+        return out[1 + self.n_par:], out[0], out[1:1 + self.n_par]
+
+    def partials(self, theta, v=None):
+        """(hi, lo) pairs of [F, G, dF, dG, H_F v, H_G v] (eq. (5) and derivatives)."""
+        t = self._theta(theta)
+        vv = self._theta(v) if v is not None else None
+        out = torch.empty(2 * (2 + 4 * self.n_par), dtype=torch.float64, device=self.device)
+        L.check("pwa_partials", self.lib.pwa_partials(self._h, _ptr(t), _ptr(vv), _ptr(out), _stream()))
+        return out
+
+    def combine(self, parts, n_data_total, n_mc_total, v=None):
+        return combine(parts, self.n_par, n_data_total, n_mc_total, v, self.device)
+
+    def device_status(self):
+        s = self.lib.pwa_device_status(self._h, _stream())
+        if s < 0:
+            L.check("pwa_device_status", s)
+        return s
+
+    # ------------------------------------------------------------------- fit
+    def fit(self, theta0, xtol=1e-8, maxiter=200, cg_maxiter=0, time_cap_s=0.0,
+            hvp_precision="f64", free_mask=None):
+        """Newton-CG fit from theta0; returns (theta, report dict)."""
+        t = self._theta(theta0).clone()
+        o = L.PwaFitOpts()
+        o.xtol = xtol
+        o.maxiter = maxiter
+        o.cg_maxiter = cg_maxiter
+        o.time_cap_s = time_cap_s
+        o.hvp_precision = L.PWA_PREC_F32 if hvp_precision == "f32" else L.PWA_PREC_F64
+        o.free_mask_set = 0 if free_mask is None else 1
+        if free_mask is not None:
+            for i, f in enumerate(free_mask):
+                o.free_mask[i] = 1 if f else 0
+        rep = L.PwaFitReport()
+        code = self.lib.pwa_fit(self._h, _ptr(t), ctypes.byref(o), ctypes.byref(rep), _stream())
+        if code not in (L.PWA_OK, L.PWA_E_NOCONV, L.PWA_E_DOMAIN):
+            L.check("pwa_fit", code)
+        report = {f: getattr(rep, f) for f, _ in L.PwaFitReport._fields_}
+        report["code"] = int(code)
+        return t, report
+
+
+def combine(parts, n_par, n_data_total, n_mc_total, v=None, device="cuda"):
+    """Eq. (4), (6), (7) over shard partials (list of pwa_partials outputs)."""
+    lib = L.load()
+    stacked = torch.cat([p.reshape(-1) for p in parts]).contiguous()
+    out = torch.empty(1 + 2 * n_par, dtype=torch.float64, device=device)
+    base = out.data_ptr()
+    vv = _dev_f64(v, device) if v is not None else None
+    L.check("pwa_combine", lib.pwa_combine(
+        n_par, len(parts), _ptr(stacked), int(n_data_total), int(n_mc_total), _ptr(vv),
+        ctypes.c_void_p(base), ctypes.c_void_p(base + 8),
+        ctypes.c_void_p(base + 8 * (1 + n_par)) if v is not None else None, _stream()))
+    return out[0], out[1:1 + n_par], (out[1 + n_par:] if v is not None else None)

@@ -1,0 +1,743 @@
+// Host side of the PWA likelihood library: argument validation, workspace
+// layout, stream-ordered launches and the Newton-CG fit driver.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "pwa_internal.h"
+
+using namespace pwa;
+
+struct pwa_ctx {
+  pwa_model model;
+  int32_t streams = 0;
+  int32_t precision = PWA_PREC_F64;
+  int K = 0, P = 0;
+  ModelDev md;
+  FieldSpec fs;
+  int shape_T = 0, shape_R = 0;  // 0 = automatic
+  // bound state
+  bool bound = false;
+  int64_t n_data = 0, n_mc = 0, stride = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* status = nullptr;
+  double* tbl64 = nullptr;
+  float* tbl32 = nullptr;
+  int* itbl = nullptr;
+  double* part = nullptr;
+  double* dd = nullptr;
+  double* scratch = nullptr;
+  double* planes64 = nullptr;
+  float* planes32 = nullptr;
+  int cu_count = 0;
+  int grid_cache[2][3][32];      // [prec][mode][shape index] -> blocks (0 = unknown)
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int ev_used = 0;
+  double timed_ms = 0.0;
+  int64_t timed_n = 0;
+  ~pwa_ctx() {
+    for (auto e : ev_start) hipEventDestroy(e);
+    for (auto e : ev_stop) hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+struct Layout {
+  size_t status, tbl64, tbl32, itbl, part, dd, scratch, planes64, planes32, total;
+  int64_t stride;
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+Layout layout_of(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  const int K = c->K, P = c->P;
+  L.status = take(64 * sizeof(int));
+  L.tbl64 = take(sizeof(double) * KPAD * TS);
+  L.tbl32 = take(sizeof(float) * KPAD * TS);
+  L.itbl = take(sizeof(int) * KPAD * ITS);
+  L.part = take(sizeof(double) * 2 * (size_t)MAX_BLOCKS * (1 + 8 * (size_t)K));
+  L.dd = take(sizeof(double) * 2 * (2 + 4 * (size_t)P));
+  L.scratch = take(sizeof(double) * (8 * (size_t)P + 16));
+  L.stride = (int64_t)align_up((size_t)(n_data + n_mc), 64);
+  L.planes64 = take((c->streams & PWA_STREAM_F64) ? sizeof(double) * (size_t)c->fs.n_fields * L.stride : 0);
+  L.planes32 = take((c->streams & PWA_STREAM_F32) ? sizeof(float) * (size_t)c->fs.n_fields * L.stride : 0);
+  L.total = off;
+  return L;
+}
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+// Shape index within the built list (for the grid cache).
+const int kShapes[][2] = {{1, 2}, {1, 4}, {1, 8}, {1, 12}, {2, 4}, {2, 6}, {4, 2},
+                          {4, 3}, {4, 4}, {8, 2}, {8, 4}, {8, 8}, {16, 4}};
+const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+int shape_index(int T, int R) {
+  for (int i = 0; i < kNumShapes; ++i)
+    if (kShapes[i][0] == T && kShapes[i][1] == R) return i;
+  return -1;
+}
+
+// Automatic launch shape: the smallest built (T, R) covering K, preferring
+// few lanes per event (less duplicated per-event work) while keeping the
+// per-lane FP64 accumulators (8R for the HVP) small enough for 2+ waves/SIMD.
+void auto_shape(int K, int& T, int& R) {
+  if (K <= 2) { T = 1; R = 2; return; }
+  if (K <= 4) { T = 1; R = 4; return; }
+  if (K <= 8) { T = 2; R = 4; return; }
+  if (K <= 12) { T = 4; R = 3; return; }
+  if (K <= 16) { T = 4; R = 4; return; }
+  if (K <= 32) { T = 8; R = 4; return; }
+  T = 16; R = 4;
+}
+
+void shape_of(const pwa_ctx* c, int& T, int& R) {
+  if (c->shape_T > 0) {
+    T = c->shape_T;
+    R = c->shape_R;
+  } else {
+    auto_shape(c->K, T, R);
+  }
+}
+
+int grid_blocks(pwa_ctx* c, int prec, int mode, int T, int R) {
+  const int si = (mode == MODE_NLL) ? 0 : shape_index(T, R);
+  int& cached = c->grid_cache[prec][mode][si < 0 ? 0 : si];
+  if (cached == 0) {
+    int occ = eval_occupancy(prec, mode, T, R);
+    if (occ <= 0) occ = 1;
+    cached = std::max(1, std::min(MAX_BLOCKS, c->cu_count * occ));
+  }
+  const int teams = (mode == MODE_NLL) ? BLOCK : BLOCK / T;
+  const int64_t n = c->n_data + c->n_mc;
+  const int64_t need = std::max<int64_t>(2, (n + teams - 1) / teams);
+  return (int)std::min<int64_t>(cached, need);
+}
+
+void split_blocks(const pwa_ctx* c, int nb, int& nb_data, int& nb_mc) {
+  if (c->n_data == 0) {
+    nb_data = 0;
+    nb_mc = std::max(1, nb);
+    return;
+  }
+  // data events cost a logarithm and a reciprocal more: weight them 1.2
+  const double wd = 1.2 * (double)c->n_data, wm = (double)c->n_mc;
+  nb_data = (int)llround(nb * wd / (wd + wm));
+  nb_data = std::max(1, std::min(nb - 1, nb_data));
+  nb_mc = std::max(1, nb - nb_data);
+}
+
+constexpr int kEventPool = 256;
+
+// Fold the durations of all recorded event pairs into the running total.
+int fold_timing(pwa_ctx* c) {
+  if (c->ev_used == 0) return PWA_OK;
+  if (hipEventSynchronize(c->ev_stop[c->ev_used - 1]) != hipSuccess) return PWA_E_HIP;
+  for (int i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]) != hipSuccess) return PWA_E_HIP;
+    c->timed_ms += ms;
+    ++c->timed_n;
+  }
+  c->ev_used = 0;
+  return PWA_OK;
+}
+
+int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta,
+             const double* d_v, double* d_nll, double* d_grad, double* d_hv, double* d_dd,
+             hipStream_t st) {
+  int T = 1, R = 1;
+  if (mode != MODE_NLL) shape_of(c, T, R);
+  const int kslots = (mode == MODE_NLL) ? c->K : T * R;
+  hipError_t e = launch_table(d_theta, d_v, c->md, kslots, c->tbl64, c->tbl32, c->itbl, c->status, st);
+  if (e != hipSuccess) return PWA_E_HIP;
+  const int nb = grid_blocks(c, prec, mode, T, R);
+  EvalArgs a;
+  a.planes = prec == PWA_PREC_F32 ? (const void*)c->planes32 : (const void*)c->planes64;
+  a.stride = c->stride;
+  a.tbl64 = c->tbl64;
+  a.tbl32 = c->tbl32;
+  a.itbl = c->itbl;
+  a.n_data = c->n_data;
+  a.n_mc = c->n_mc;
+  split_blocks(c, nb, a.nb_data, a.nb_mc);
+  a.K = c->K;
+  a.part = c->part;
+  const bool timed = c->timing;
+  if (timed) {
+    if (c->ev_used == kEventPool && fold_timing(c) != PWA_OK) return PWA_E_HIP;
+    if (hipEventRecord(c->ev_start[c->ev_used], st) != hipSuccess) return PWA_E_HIP;
+  }
+  e = launch_eval(prec, mode, T, R, a, a.nb_data + a.nb_mc, st);
+  if (e != hipSuccess) return PWA_E_HIP;
+  if (timed) {
+    if (hipEventRecord(c->ev_stop[c->ev_used], st) != hipSuccess) return PWA_E_HIP;
+    ++c->ev_used;
+  }
+  FinalArgs f;
+  f.part = c->part;
+  f.nb_data = a.nb_data;
+  f.nb_mc = a.nb_mc;
+  f.V = 1 + (mode >= MODE_GRAD ? 4 * c->K : 0) + (mode == MODE_HVP ? 4 * c->K : 0);
+  f.K = c->K;
+  f.mode = mode;
+  f.out_kind = out_kind;
+  f.n_data = (double)c->n_data;
+  f.n_mc = (double)c->n_mc;
+  f.v = d_v;
+  f.nll = d_nll;
+  f.grad = d_grad;
+  f.hv = d_hv;
+  f.dd_out = d_dd;
+  f.status = c->status;
+  e = launch_final(f, st);
+  return e == hipSuccess ? PWA_OK : PWA_E_HIP;
+}
+
+int check_prec(const pwa_ctx* c, int prec) {
+  if (prec == PWA_PREC_F64) return (c->streams & PWA_STREAM_F64) ? PWA_OK : PWA_E_INVALID;
+  if (prec == PWA_PREC_F32) return (c->streams & PWA_STREAM_F32) ? PWA_OK : PWA_E_INVALID;
+  return PWA_E_INVALID;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pwa_status_str(int s) {
+  switch (s) {
+    case PWA_OK: return "ok";
+    case PWA_E_INVALID: return "invalid argument";
+    case PWA_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case PWA_E_HIP: return "HIP runtime error";
+    case PWA_E_DOMAIN: return "NLL not finite at the start point";
+    case PWA_E_NOCONV: return "fit stopped before meeting xtol";
+    case PWA_E_STATE: return "context not bound to events";
+    default: return "unknown status";
+  }
+}
+
+int pwa_create(const pwa_model* m, int32_t streams, pwa_ctx** out) {
+  if (!m || !out) return PWA_E_INVALID;
+  *out = nullptr;
+  if (m->n_res < 1 || m->n_res > PWA_MAX_RES) return PWA_E_INVALID;
+  if (!(streams & (PWA_STREAM_F64 | PWA_STREAM_F32)) || (streams & ~3)) return PWA_E_INVALID;
+  if (m->width_mode != PWA_WIDTH_MASS_DEPENDENT && m->width_mode != PWA_WIDTH_CONSTANT)
+    return PWA_E_INVALID;
+  if (!finite_pos(m->parent_mass) || !finite_pos(m->r)) return PWA_E_INVALID;
+  for (int i = 0; i < 3; ++i)
+    if (!finite_pos(m->masses[i])) return PWA_E_INVALID;
+  if (!(m->parent_mass > m->masses[0] + m->masses[1] + m->masses[2])) return PWA_E_INVALID;
+  for (int k = 0; k < m->n_res; ++k) {
+    if (m->channel[k] < 0 || m->channel[k] > 2) return PWA_E_INVALID;
+    if (m->spin[k] < 0 || m->spin[k] > 2) return PWA_E_INVALID;
+  }
+  pwa_ctx* c = new (std::nothrow) pwa_ctx();
+  if (!c) return PWA_E_INVALID;
+  c->model = *m;
+  c->streams = streams;
+  c->precision = (streams & PWA_STREAM_F64) ? PWA_PREC_F64 : PWA_PREC_F32;
+  c->K = m->n_res;
+  c->P = 4 * m->n_res;
+  memset(c->grid_cache, 0, sizeof(c->grid_cache));
+  // field layout: s per channel, g per (channel, J), u per (channel, J >= 1)
+  FieldSpec& fs = c->fs;
+  for (int ch = 0; ch < 3; ++ch) {
+    fs.s_field[ch] = -1;
+    for (int J = 0; J < 3; ++J) fs.u_field[ch][J] = fs.g_field[ch][J] = -1;
+  }
+  int nf = 0;
+  for (int k = 0; k < c->K; ++k) {
+    const int ch = m->channel[k], J = m->spin[k];
+    if (fs.s_field[ch] < 0) fs.s_field[ch] = nf++;
+    if (fs.g_field[ch][J] < 0) {
+      fs.g_field[ch][J] = nf++;
+      if (J >= 1) fs.u_field[ch][J] = nf++;
+    }
+  }
+  fs.n_fields = nf;
+  ModelDev& md = c->md;
+  memset(&md, 0, sizeof(md));
+  md.M2 = m->parent_mass * m->parent_mass;
+  for (int i = 0; i < 3; ++i) {
+    md.m[i] = m->masses[i];
+    md.msq[i] = m->masses[i] * m->masses[i];
+  }
+  md.r2 = m->r * m->r;
+  md.K = c->K;
+  md.width_mode = m->width_mode;
+  for (int k = 0; k < c->K; ++k) {
+    const int ch = m->channel[k], J = m->spin[k];
+    md.ch[k] = ch;
+    md.spin[k] = J;
+    md.fidx[k][0] = fs.s_field[ch];
+    md.fidx[k][1] = J >= 1 ? fs.u_field[ch][J] : fs.s_field[ch];
+    md.fidx[k][2] = fs.g_field[ch][J];
+  }
+  *out = c;
+  return PWA_OK;
+}
+
+void pwa_destroy(pwa_ctx* c) { delete c; }
+
+int32_t pwa_n_par(const pwa_ctx* c) { return c ? c->P : -1; }
+
+size_t pwa_workspace_bytes(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
+  if (!c || n_data < 0 || n_mc < 1) return 0;
+  if (n_data > ((int64_t)1 << 40) || n_mc > ((int64_t)1 << 40)) return 0;
+  return layout_of(c, n_data, n_mc).total;
+}
+
+int pwa_bind(pwa_ctx* c, const double* d_s12, const double* d_s13, int64_t n_data,
+             const double* d_mc_s12, const double* d_mc_s13, int64_t n_mc, void* d_ws,
+             size_t ws_bytes, hipStream_t st) {
+  if (!c || n_data < 0 || n_mc < 1) return PWA_E_INVALID;
+  if (n_data > 0 && (!d_s12 || !d_s13)) return PWA_E_INVALID;
+  if (!d_mc_s12 || !d_mc_s13) return PWA_E_INVALID;
+  if (n_data > ((int64_t)1 << 40) || n_mc > ((int64_t)1 << 40)) return PWA_E_INVALID;
+  if (!d_ws || ((uintptr_t)d_ws % 256) != 0) return PWA_E_WORKSPACE;
+  const Layout L = layout_of(c, n_data, n_mc);
+  if (ws_bytes < L.total) return PWA_E_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PWA_E_HIP;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return PWA_E_HIP;
+  c->cu_count = cus;
+  c->bound = false;
+  c->n_data = n_data;
+  c->n_mc = n_mc;
+  c->stride = L.stride;
+  c->ws = (char*)d_ws;
+  c->ws_bytes = ws_bytes;
+  c->status = (int*)(c->ws + L.status);
+  c->tbl64 = (double*)(c->ws + L.tbl64);
+  c->tbl32 = (float*)(c->ws + L.tbl32);
+  c->itbl = (int*)(c->ws + L.itbl);
+  c->part = (double*)(c->ws + L.part);
+  c->dd = (double*)(c->ws + L.dd);
+  c->scratch = (double*)(c->ws + L.scratch);
+  c->planes64 = (c->streams & PWA_STREAM_F64) ? (double*)(c->ws + L.planes64) : nullptr;
+  c->planes32 = (c->streams & PWA_STREAM_F32) ? (float*)(c->ws + L.planes32) : nullptr;
+  memset(c->grid_cache, 0, sizeof(c->grid_cache));
+  if (hipMemsetAsync(c->status, 0, 64 * sizeof(int), st) != hipSuccess) return PWA_E_HIP;
+  for (int f32 = 0; f32 < 2; ++f32) {
+    void* planes = f32 ? (void*)c->planes32 : (void*)c->planes64;
+    if (!planes) continue;
+    if (launch_precompute(d_s12, d_s13, n_data, 0, planes, L.stride, f32, c->md, c->fs, st) != hipSuccess)
+      return PWA_E_HIP;
+    if (launch_precompute(d_mc_s12, d_mc_s13, n_mc, n_data, planes, L.stride, f32, c->md, c->fs, st) != hipSuccess)
+      return PWA_E_HIP;
+  }
+  c->bound = true;
+  return PWA_OK;
+}
+
+int pwa_set_precision(pwa_ctx* c, int32_t prec) {
+  if (!c) return PWA_E_INVALID;
+  if (check_prec(c, prec) != PWA_OK) return PWA_E_INVALID;
+  c->precision = prec;
+  return PWA_OK;
+}
+
+int pwa_set_launch_shape(pwa_ctx* c, int32_t T, int32_t R) {
+  if (!c) return PWA_E_INVALID;
+  if (T == 0 && R == 0) {
+    c->shape_T = c->shape_R = 0;
+    return PWA_OK;
+  }
+  if (!shape_built(T, R) || T * R < c->K || T * R > KPAD) return PWA_E_INVALID;
+  c->shape_T = T;
+  c->shape_R = R;
+  return PWA_OK;
+}
+
+int32_t pwa_grid_blocks(const pwa_ctx* c) {
+  if (!c || !c->bound) return -1;
+  int T, R;
+  shape_of(c, T, R);
+  return grid_blocks(const_cast<pwa_ctx*>(c), c->precision, MODE_HVP, T, R);
+}
+
+int pwa_set_kernel_timing(pwa_ctx* c, int32_t enable) {
+  if (!c) return PWA_E_INVALID;
+  if (enable && c->ev_start.empty()) {
+    c->ev_start.resize(kEventPool);
+    c->ev_stop.resize(kEventPool);
+    for (int i = 0; i < kEventPool; ++i)
+      if (hipEventCreate(&c->ev_start[i]) != hipSuccess || hipEventCreate(&c->ev_stop[i]) != hipSuccess)
+        return PWA_E_HIP;
+  }
+  c->timing = enable != 0;
+  return PWA_OK;
+}
+
+int pwa_kernel_time(pwa_ctx* c, double* total_ms, int64_t* n) {
+  if (!c || !total_ms || !n) return PWA_E_INVALID;
+  const int s = fold_timing(c);
+  if (s != PWA_OK) return s;
+  *total_ms = c->timed_ms;
+  *n = c->timed_n;
+  c->timed_ms = 0.0;
+  c->timed_n = 0;
+  return PWA_OK;
+}
+
+int pwa_nll(pwa_ctx* c, const double* d_theta, double* d_nll, hipStream_t st) {
+  if (!c || !d_theta || !d_nll) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  return run_eval(c, MODE_NLL, OUT_COMBINED, c->precision, d_theta, nullptr, d_nll, nullptr,
+                  nullptr, nullptr, st);
+}
+
+int pwa_grad(pwa_ctx* c, const double* d_theta, double* d_nll, double* d_grad, hipStream_t st) {
+  if (!c || !d_theta || !d_grad) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  return run_eval(c, MODE_GRAD, OUT_COMBINED, c->precision, d_theta, nullptr, d_nll, d_grad,
+                  nullptr, nullptr, st);
+}
+
+int pwa_hvp(pwa_ctx* c, const double* d_theta, const double* d_v, double* d_hv, double* d_nll,
+            double* d_grad, hipStream_t st) {
+  if (!c || !d_theta || !d_v || !d_hv) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  return run_eval(c, MODE_HVP, OUT_COMBINED, c->precision, d_theta, d_v, d_nll, d_grad, d_hv,
+                  nullptr, st);
+}
+
+int pwa_partials(pwa_ctx* c, const double* d_theta, const double* d_v, double* d_part,
+                 hipStream_t st) {
+  if (!c || !d_theta || !d_part) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  return run_eval(c, d_v ? MODE_HVP : MODE_GRAD, OUT_PARTIALS, c->precision, d_theta, d_v,
+                  nullptr, nullptr, nullptr, d_part, st);
+}
+
+int pwa_combine(int32_t n_par, int32_t n_shards, const double* d_parts, int64_t n_data_total,
+                int64_t n_mc_total, const double* d_v, double* d_nll, double* d_grad,
+                double* d_hv, hipStream_t st) {
+  if (n_par < 4 || n_par > 4 * PWA_MAX_RES || (n_par % 4) != 0) return PWA_E_INVALID;
+  if (n_shards < 1 || !d_parts || !d_nll) return PWA_E_INVALID;
+  if (n_data_total < 0 || n_mc_total < 1) return PWA_E_INVALID;
+  if (d_hv && (!d_v || !d_grad)) return PWA_E_INVALID;
+  return launch_combine(n_par, n_shards, d_parts, (double)n_data_total, (double)n_mc_total, d_v,
+                        d_nll, d_grad, d_hv, nullptr, st) == hipSuccess
+             ? PWA_OK
+             : PWA_E_HIP;
+}
+
+int pwa_device_status(pwa_ctx* c, hipStream_t st) {
+  if (!c) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  int h = 0;
+  if (hipMemcpyAsync(&h, c->status + 1, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return PWA_E_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return PWA_E_HIP;
+  if (hipMemsetAsync(c->status + 1, 0, sizeof(int), st) != hipSuccess) return PWA_E_HIP;
+  return h;
+}
+
+// ---------------------------------------------------------------------------
+// Newton-CG fit.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Fitter {
+  pwa_ctx* c;
+  hipStream_t st;
+  int P;
+  std::vector<unsigned char> free_;
+  double* d_x;   // device scratch
+  double* d_v;
+  double* d_out; // [nll, grad(P), hv(P)]
+  int prec_hvp;
+  int prec_main;
+  int n_nll = 0, n_grad = 0, n_hvp = 0;
+  int err = PWA_OK;
+
+  void mask(std::vector<double>& g) const {
+    for (int i = 0; i < P; ++i)
+      if (!free_[i]) g[i] = 0.0;
+  }
+  bool up(const std::vector<double>& x, double* d) {
+    if (hipMemcpyAsync(d, x.data(), sizeof(double) * P, hipMemcpyHostToDevice, st) != hipSuccess) {
+      err = PWA_E_HIP;
+      return false;
+    }
+    return true;
+  }
+  bool down(double* h, const double* d, int n) {
+    if (hipMemcpyAsync(h, d, sizeof(double) * n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      err = PWA_E_HIP;
+      return false;
+    }
+    return true;
+  }
+  // f and gradient at x (FP64 unless only FP32 exists)
+  bool fg(const std::vector<double>& x, double& f, std::vector<double>& g) {
+    if (!up(x, d_x)) return false;
+    if (run_eval(c, MODE_GRAD, OUT_COMBINED, prec_main, d_x, nullptr, d_out, d_out + 1, nullptr,
+                 nullptr, st) != PWA_OK) {
+      err = PWA_E_HIP;
+      return false;
+    }
+    std::vector<double> buf(1 + P);
+    if (!down(buf.data(), d_out, 1 + P)) return false;
+    ++n_grad;
+    f = buf[0];
+    g.assign(buf.begin() + 1, buf.end());
+    mask(g);
+    return true;
+  }
+  bool hvp(const std::vector<double>& x_on_device_dummy, const std::vector<double>& p,
+           std::vector<double>& hp) {
+    (void)x_on_device_dummy;
+    if (!up(p, d_v)) return false;
+    if (run_eval(c, MODE_HVP, OUT_COMBINED, prec_hvp, d_x, d_v, nullptr, nullptr,
+                 d_out + 1 + P, nullptr, st) != PWA_OK) {
+      err = PWA_E_HIP;
+      return false;
+    }
+    hp.resize(P);
+    if (!down(hp.data(), d_out + 1 + P, P)) return false;
+    ++n_hvp;
+    mask(hp);
+    return true;
+  }
+};
+
+double dot(const std::vector<double>& a, const std::vector<double>& b) {
+  double s = 0.0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
+double sum_abs(const std::vector<double>& a) {
+  double s = 0.0;
+  for (double x : a) s += fabs(x);
+  return s;
+}
+
+// Minimiser of the cubic interpolating (a, fa, ga), (b, fb, gb); NaN if none.
+double cubic_min(double a, double fa, double ga, double b, double fb, double gb) {
+  const double d1 = ga + gb - 3.0 * (fa - fb) / (a - b);
+  const double disc = d1 * d1 - ga * gb;
+  if (!(disc >= 0.0)) return NAN;
+  const double d2 = copysign(sqrt(disc), b - a);
+  return b - (b - a) * (gb + d2 - d1) / (gb - ga + 2.0 * d2);
+}
+
+// Strong-Wolfe line search (Nocedal & Wright, Alg. 3.5 with the zoom of
+// Alg. 3.6 and cubic interpolation), c1 = 1e-4, c2 = 0.9, first step 1.
+// Evaluates f and its gradient at every trial point (one fused pass each).
+bool wolfe(Fitter& F, const std::vector<double>& x, double f0, const std::vector<double>& g0,
+           const std::vector<double>& p, double& alpha, double& f1, std::vector<double>& g1,
+           std::vector<double>& x1) {
+  const double c1 = 1e-4, c2 = 0.9;
+  const double d0 = dot(g0, p);
+  if (!(d0 < 0.0)) return false;
+  auto eval = [&](double a, double& fa, double& da, std::vector<double>& ga) {
+    x1.resize(x.size());
+    for (size_t i = 0; i < x.size(); ++i) x1[i] = x[i] + a * p[i];
+    if (!F.fg(x1, fa, ga)) return false;
+    if (!isfinite(fa)) {
+      fa = INFINITY;
+      da = NAN;
+    } else {
+      da = dot(ga, p);
+    }
+    return true;
+  };
+  double a_prev = 0.0, f_prev = f0, d_prev = d0;
+  double a = 1.0;
+  std::vector<double> ga;
+  double lo = 0, hi = 0, flo = 0, fhi = 0, dlo = 0, dhi = 0;
+  bool zoom = false;
+  for (int i = 0; i < 30; ++i) {
+    double fa, da;
+    if (!eval(a, fa, da, ga)) return false;
+    if (!isfinite(fa) || fa > f0 + c1 * a * d0 || (i > 0 && fa >= f_prev)) {
+      lo = a_prev; flo = f_prev; dlo = d_prev;
+      hi = a; fhi = fa; dhi = da;
+      zoom = true;
+      break;
+    }
+    if (fabs(da) <= -c2 * d0) {
+      alpha = a; f1 = fa; g1 = ga;
+      return true;
+    }
+    if (da >= 0.0) {
+      lo = a; flo = fa; dlo = da;
+      hi = a_prev; fhi = f_prev; dhi = d_prev;
+      zoom = true;
+      break;
+    }
+    a_prev = a; f_prev = fa; d_prev = da;
+    a *= 2.0;
+  }
+  if (!zoom) return false;
+  for (int i = 0; i < 40; ++i) {
+    double at = NAN;
+    if (isfinite(fhi) && isfinite(dhi)) at = cubic_min(lo, flo, dlo, hi, fhi, dhi);
+    const double lo_b = std::min(lo, hi), hi_b = std::max(lo, hi), w = hi_b - lo_b;
+    if (!(at > lo_b + 0.1 * w && at < hi_b - 0.1 * w)) at = 0.5 * (lo + hi);
+    double fa, da;
+    if (!eval(at, fa, da, ga)) return false;
+    if (!isfinite(fa) || fa > f0 + c1 * at * d0 || fa >= flo) {
+      hi = at; fhi = fa; dhi = da;
+    } else {
+      if (fabs(da) <= -c2 * d0) {
+        alpha = at; f1 = fa; g1 = ga;
+        return true;
+      }
+      if (da * (hi - lo) >= 0.0) {
+        hi = lo; fhi = flo; dhi = dlo;
+      }
+      lo = at; flo = fa; dlo = da;
+    }
+    if (fabs(hi - lo) < 1e-16 * std::max(1.0, fabs(lo))) break;
+  }
+  // accept the best point with sufficient decrease, if any
+  if (lo > 0.0 && flo < f0) {
+    double fa, da;
+    if (!eval(lo, fa, da, ga)) return false;
+    alpha = lo; f1 = fa; g1 = ga;
+    return true;
+  }
+  return false;
+}
+
+}  // namespace
+
+int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* rep,
+            hipStream_t st) {
+  if (!c || !d_theta || !o) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  if (!(o->xtol > 0.0) || !isfinite(o->xtol)) return PWA_E_INVALID;
+  const int hp = o->hvp_precision;
+  if (check_prec(c, hp) != PWA_OK) return PWA_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto elapsed = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  const int P = c->P;
+  Fitter F;
+  F.c = c;
+  F.st = st;
+  F.P = P;
+  F.free_.assign(P, 1);
+  if (o->free_mask_set)
+    for (int i = 0; i < P; ++i) F.free_[i] = o->free_mask[i] ? 1 : 0;
+  F.d_x = c->scratch;
+  F.d_v = c->scratch + P;
+  F.d_out = c->scratch + 2 * P;
+  F.prec_hvp = hp;
+  F.prec_main = (c->streams & PWA_STREAM_F64) ? PWA_PREC_F64 : PWA_PREC_F32;
+  const int maxiter = o->maxiter > 0 ? o->maxiter : 200;
+  const int cg_max = o->cg_maxiter > 0 ? o->cg_maxiter : 20 * P;
+
+  std::vector<double> x(P), g, best_x;
+  if (hipMemcpyAsync(x.data(), d_theta, sizeof(double) * P, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return PWA_E_HIP;
+  double f;
+  int status = PWA_OK, converged = 0, it = 0;
+  if (!F.fg(x, f, g)) return F.err;
+  if (!isfinite(f)) status = PWA_E_DOMAIN;
+  best_x = x;
+  double best_f = f;
+  std::vector<double> r(P), pcg(P), xs(P), Ap, x1, g1;
+  while (status == PWA_OK) {
+    if (it >= maxiter) { status = PWA_E_NOCONV; break; }
+    if (o->time_cap_s > 0 && elapsed() > o->time_cap_s) { status = PWA_E_NOCONV; break; }
+    // truncated CG on H p = -g (scipy's forcing term and curvature tests)
+    const double maggrad = sum_abs(g);
+    const double eta = std::min(0.5, sqrt(maggrad));
+    const double termcond = eta * maggrad;
+    std::fill(xs.begin(), xs.end(), 0.0);
+    r = g;
+    for (int i = 0; i < P; ++i) pcg[i] = -g[i];
+    double dri0 = dot(r, r);
+    // the HVPs are taken at x: upload x once
+    if (!F.up(x, F.d_x)) return F.err;
+    for (int k = 0, i = 0; k < cg_max; ++k) {
+      if (sum_abs(r) <= termcond) break;
+      if (!F.hvp(x, pcg, Ap)) return F.err;
+      const double curv = dot(pcg, Ap);
+      if (0.0 <= curv && curv <= 3.0 * 2.220446049250313e-16) break;
+      if (curv < 0.0) {
+        if (i > 0) break;
+        for (int j = 0; j < P; ++j) xs[j] = dri0 / (-curv) * (-g[j]);
+        break;
+      }
+      const double al = dri0 / curv;
+      for (int j = 0; j < P; ++j) {
+        xs[j] += al * pcg[j];
+        r[j] += al * Ap[j];
+      }
+      const double dri1 = dot(r, r);
+      const double be = dri1 / dri0;
+      for (int j = 0; j < P; ++j) pcg[j] = -r[j] + be * pcg[j];
+      ++i;
+      dri0 = dri1;
+    }
+    if (sum_abs(xs) == 0.0) {  // already stationary
+      converged = 1;
+      break;
+    }
+    double alpha, f1;
+    if (!wolfe(F, x, f, g, xs, alpha, f1, g1, x1)) {
+      if (F.err != PWA_OK) return F.err;
+      status = PWA_E_NOCONV;
+      break;
+    }
+    double upd = 0.0;
+    for (int j = 0; j < P; ++j) upd += fabs(alpha * xs[j]);
+    x = x1;
+    f = f1;
+    g = g1;
+    ++it;
+    if (f < best_f) { best_f = f; best_x = x; }
+    if (upd <= P * o->xtol) { converged = 1; break; }
+  }
+  if (status == PWA_E_DOMAIN) best_x = x;
+  if (hipMemcpyAsync(d_theta, best_x.data(), sizeof(double) * P, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return PWA_E_HIP;
+  if (rep) {
+    double gm = 0.0;
+    std::vector<double> gb;
+    double fb = best_f;
+    if (status != PWA_E_DOMAIN && F.fg(best_x, fb, gb))
+      for (int j = 0; j < P; ++j) gm = std::max(gm, fabs(gb[j]));
+    rep->nll = fb;
+    rep->grad_max = gm;
+    rep->seconds = elapsed();
+    rep->iterations = it;
+    rep->n_nll = F.n_nll;
+    rep->n_grad = F.n_grad;
+    rep->n_hvp = F.n_hvp;
+    rep->status = converged ? PWA_OK : status;
+    rep->converged = converged;
+  }
+  if (converged) return PWA_OK;
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal declarations shared by the kernel and host translation units of
+// the PWA likelihood library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pwa.h"
+
+namespace pwa {
+
+// ---------------------------------------------------------------- table --
+// Per-resonance constants built on the device from (theta, v) before every
+// evaluation.  Factorised Breit-Wigner: with the per-event stream values
+//   s (pair mass^2), u = F_J(z) P_J(cos), g = q^(2J+1) F_J(z)^2 / sqrt(s)
+// and the per-resonance functions of M only
+//   eta(M) = M^2 / (q0^(2J+1) F_J(z0)^2),  beta(M) = 1/F_J(z0),
+// one has M Gamma(s) = Gamma eta g, and the amplitude is
+//   a = beta u / D,  D = (M^2 - s) - i Gamma eta g.
+// Entries are laid out in the order the kernel consumes them.
+enum TableSlot : int {
+  TB_M2 = 0,      // M^2
+  TB_NGE = 1,     // -Gamma eta           (Im D = TB_NGE * g)
+  TB_BETA = 2,    // beta
+  TB_CR = 3,      // Re c
+  TB_CI = 4,      // Im c
+  TB_UMUL = 5,    // u = u_plane * UMUL + UADD (J = 0: u = 1)
+  TB_UADD = 6,
+  TB_DDR = 7,     // directional derivative of D along v: (DDR, DDIG * g)
+  TB_DDIG = 8,
+  TB_BDOT = 9,    // v_M beta'
+  TB_VR = 10,     // v on Re c, Im c
+  TB_VI = 11,
+  TB_2M = 12,     // dD/dM = (2M, NGE1 * g)
+  TB_NGE1 = 13,   // -Gamma eta'
+  TB_NETA = 14,   // dD/dGamma = (0, NETA * g), NETA = -eta
+  TB_BETA1 = 15,  // beta'
+  TB_DMDDR = 16,  // d/dM of the directional derivative: (DMDDR, DMDDIG * g)
+  TB_DMDDIG = 17,
+  TB_DGDDIG = 18, // d/dGamma of the directional derivative: (0, DGDDIG * g)
+  TB_BDOT1 = 19,  // v_M beta''
+  TB_USED = 20
+};
+constexpr int TS = 24;        // table stride (reals) per resonance
+constexpr int ITS = 4;        // int table stride: s plane, u plane, g plane, J
+constexpr int KPAD = 64;      // table rows (resonance slots incl. padding)
+constexpr int BLOCK = 256;    // threads per block of the evaluation kernels
+constexpr int MAX_BLOCKS = 4096;
+
+// Evaluation modes.
+enum Mode : int { MODE_NLL = 0, MODE_GRAD = 1, MODE_HVP = 2 };
+
+// Output kinds of the finaliser.
+enum OutKind : int { OUT_COMBINED = 0, OUT_PARTIALS = 1 };
+
+// Physical constants of the model, passed by value to kernels.
+struct ModelDev {
+  double M2;                 // parent mass^2
+  double msq[3];             // daughter masses^2
+  double m[3];
+  double r2;                 // Blatt-Weisskopf radius^2
+  int K;
+  int width_mode;
+  int ch[PWA_MAX_RES];
+  int spin[PWA_MAX_RES];
+  int fidx[PWA_MAX_RES][3];  // s, u, g plane of each resonance (u = s for J = 0)
+};
+
+// Which planes the event stream holds.
+struct FieldSpec {
+  int s_field[3];            // -1: channel unused
+  int u_field[3][3];         // [channel][J], -1: absent (always -1 for J = 0)
+  int g_field[3][3];
+  int n_fields;
+};
+
+struct EvalArgs {
+  const void* planes;        // n_fields planes of `stride` reals
+  int64_t stride;
+  const double* tbl64;
+  const float* tbl32;
+  const int* itbl;
+  int64_t n_data, n_mc;      // data events [0, n_data), MC [n_data, n_data + n_mc)
+  int nb_data, nb_mc;
+  int K;
+  double* part;              // per-block (hi, lo) partial sums
+};
+
+struct FinalArgs {
+  const double* part;
+  int nb_data, nb_mc;
+  int V;                     // values per block: 1 (+4K) (+4K)
+  int K, mode, out_kind;
+  double n_data, n_mc;
+  const double* v;           // direction (HVP), may be null
+  double* nll;
+  double* grad;
+  double* hv;
+  double* dd_out;            // partials output (out_kind == OUT_PARTIALS)
+  int* status;               // [0] this evaluation, [1] sticky
+};
+
+// Launchers (pwa_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_precompute(const double* s12, const double* s13, int64_t n, int64_t offset,
+                             void* planes, int64_t stride, int is_f32, const ModelDev& md,
+                             const FieldSpec& fs, hipStream_t st);
+hipError_t launch_table(const double* theta, const double* v, const ModelDev& md, int kslots,
+                        double* tbl64, float* tbl32, int* itbl, int* status, hipStream_t st);
+hipError_t launch_eval(int is_f32, int mode, int T, int R, const EvalArgs& a, int nblocks,
+                       hipStream_t st);
+hipError_t launch_final(const FinalArgs& f, hipStream_t st);
+hipError_t launch_combine(int n_par, int n_shards, const double* parts, double n_data,
+                          double n_mc, const double* v, double* nll, double* grad, double* hv,
+                          int* status, hipStream_t st);
+// Maximum resident blocks per CU of an evaluation kernel variant.
+int eval_occupancy(int is_f32, int mode, int T, int R);
+// Is (T, R) an instantiated launch shape?
+bool shape_built(int T, int R);
+
+}  // namespace pwa

@@ -1,0 +1,152 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/pwa.h declares, and rejects bad arguments on the host with the
+documented status codes before any HIP call is made.  No call here reaches
+a kernel launch (fake device pointers only ever hit early validation)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2403_09225_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "pwa.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pwa_\w+)\s*\(", text)))
+
+
+def _model(K=2, channel=None, spin=None):
+    m = L.PwaModel()
+    m.parent_mass = 1.865
+    m.masses[0], m.masses[1], m.masses[2] = 0.494, 0.140, 0.140
+    m.r = 3.0
+    m.n_res = K
+    m.width_mode = 0
+    for k in range(K):
+        m.channel[k] = (channel or [k % 3] * K)[k] if channel else k % 3
+        m.spin[k] = spin[k] if spin else (k // 3) % 3
+    return m
+
+
+def _create(lib, m, streams=L.PWA_STREAM_F64):
+    h = ctypes.c_void_p()
+    code = lib.pwa_create(ctypes.byref(m), streams, ctypes.byref(h))
+    return code, h
+
+
+def test_every_declared_function_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in L.SIGNATURES, n
+
+
+def test_create_validation(lib):
+    assert lib.pwa_create(None, 1, None) == L.PWA_E_INVALID
+    for mutate in [
+        lambda m: setattr(m, "n_res", 0),
+        lambda m: setattr(m, "n_res", 65),
+        lambda m: m.channel.__setitem__(0, 3),
+        lambda m: m.spin.__setitem__(1, -1),
+        lambda m: m.masses.__setitem__(0, 0.0),
+        lambda m: setattr(m, "r", -1.0),
+        lambda m: setattr(m, "parent_mass", 0.7),
+        lambda m: setattr(m, "width_mode", 5),
+        lambda m: setattr(m, "parent_mass", float("nan")),
+    ]:
+        m = _model()
+        mutate(m)
+        code, h = _create(lib, m)
+        assert code == L.PWA_E_INVALID and not h.value
+    code, h = _create(lib, _model(), streams=0)
+    assert code == L.PWA_E_INVALID
+
+
+def test_valid_context_host_queries(lib):
+    code, h = _create(lib, _model(12), L.PWA_STREAM_F64 | L.PWA_STREAM_F32)
+    assert code == L.PWA_OK
+    try:
+        assert lib.pwa_n_par(h) == 48
+        assert lib.pwa_workspace_bytes(h, -1, 10) == 0
+        assert lib.pwa_workspace_bytes(h, 10, 0) == 0
+        a = lib.pwa_workspace_bytes(h, 1000, 5000)
+        b = lib.pwa_workspace_bytes(h, 2000, 5000)
+        # 18 planes (3 s, 6 u, 9 g) x (8 + 4) bytes per event for both streams
+        assert b - a == pytest.approx(1000 * 18 * 12, abs=2 * 64 * 18 * 12 + 512)
+        assert lib.pwa_grid_blocks(h) == -1
+        assert lib.pwa_set_precision(h, L.PWA_PREC_F32) == L.PWA_OK
+        assert lib.pwa_set_precision(h, 7) == L.PWA_E_INVALID
+        assert lib.pwa_set_launch_shape(h, 3, 3) == L.PWA_E_INVALID
+        assert lib.pwa_set_launch_shape(h, 1, 2) == L.PWA_E_INVALID   # 2 < K = 12
+        assert lib.pwa_set_launch_shape(h, 4, 3) == L.PWA_OK
+        assert lib.pwa_set_launch_shape(h, 0, 0) == L.PWA_OK
+    finally:
+        lib.pwa_destroy(h)
+    lib.pwa_destroy(None)
+
+
+def test_f64_only_context_rejects_f32(lib):
+    code, h = _create(lib, _model(2), L.PWA_STREAM_F64)
+    assert code == L.PWA_OK
+    assert lib.pwa_set_precision(h, L.PWA_PREC_F32) == L.PWA_E_INVALID
+    lib.pwa_destroy(h)
+
+
+def test_unbound_and_bad_bind_arguments(lib):
+    code, h = _create(lib, _model(2))
+    assert code == L.PWA_OK
+    fake = ctypes.c_void_p(0x100000)
+    st = None
+    try:
+        assert lib.pwa_nll(h, fake, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_grad(h, fake, fake, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_hvp(h, fake, fake, fake, None, None, st) == L.PWA_E_STATE
+        assert lib.pwa_partials(h, fake, None, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_device_status(h, st) == L.PWA_E_STATE
+        assert lib.pwa_nll(None, fake, fake, st) == L.PWA_E_INVALID
+        assert lib.pwa_nll(h, None, fake, st) == L.PWA_E_INVALID
+        assert lib.pwa_hvp(h, fake, None, fake, None, None, st) == L.PWA_E_INVALID
+        opts = L.PwaFitOpts()
+        opts.xtol = 1e-8
+        assert lib.pwa_fit(h, fake, ctypes.byref(opts), None, st) == L.PWA_E_STATE
+        assert lib.pwa_fit(h, fake, None, None, st) == L.PWA_E_INVALID
+        need = lib.pwa_workspace_bytes(h, 10, 10)
+        # n_mc < 1, negative n_data, null MC pointers
+        assert lib.pwa_bind(h, fake, fake, 10, fake, fake, 0, fake, need, st) == L.PWA_E_INVALID
+        assert lib.pwa_bind(h, fake, fake, -1, fake, fake, 10, fake, need, st) == L.PWA_E_INVALID
+        assert lib.pwa_bind(h, fake, fake, 10, None, fake, 10, fake, need, st) == L.PWA_E_INVALID
+        assert lib.pwa_bind(h, None, fake, 10, fake, fake, 10, fake, need, st) == L.PWA_E_INVALID
+        # workspace: null, misaligned, too small
+        assert lib.pwa_bind(h, fake, fake, 10, fake, fake, 10, None, need, st) == L.PWA_E_WORKSPACE
+        assert lib.pwa_bind(h, fake, fake, 10, fake, fake, 10, ctypes.c_void_p(0x100001), need,
+                            st) == L.PWA_E_WORKSPACE
+        assert lib.pwa_bind(h, fake, fake, 10, fake, fake, 10, fake, need - 1, st) == L.PWA_E_WORKSPACE
+    finally:
+        lib.pwa_destroy(h)
+
+
+def test_combine_validation(lib):
+    fake = ctypes.c_void_p(0x100000)
+    assert lib.pwa_combine(5, 1, fake, 10, 10, None, fake, None, None, None) == L.PWA_E_INVALID
+    assert lib.pwa_combine(8, 0, fake, 10, 10, None, fake, None, None, None) == L.PWA_E_INVALID
+    assert lib.pwa_combine(8, 1, None, 10, 10, None, fake, None, None, None) == L.PWA_E_INVALID
+    assert lib.pwa_combine(8, 1, fake, 10, 0, None, fake, None, None, None) == L.PWA_E_INVALID
+    assert lib.pwa_combine(8, 1, fake, 10, 10, None, fake, fake, fake, None) == L.PWA_E_INVALID
+
+
+def test_status_strings(lib):
+    for code in range(-6, 1):
+        s = lib.pwa_status_str(code)
+        assert s and len(s) >= 2
+    assert b"unknown" in lib.pwa_status_str(-99)

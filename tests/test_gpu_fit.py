@@ -1,0 +1,73 @@
+"""Newton-CG fits on the GPU (pwa_fit) against the oracle's fit with the
+paper's optimiser, scipy.optimize.minimize(method="Newton-CG") (Sec. 3),
+on the CPU-sized workload: K = 2 in channel (12) (J = 0 at 0.90/0.10 GeV,
+J = 1 at 0.892/0.05 GeV, c = (1, 0.6 e^{1.2 i})), 10k data events by
+accept-reject, 50k uniform MC events."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_cases import likelihood
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    W = synth.workload(0)
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(0, synth.configs.STREAM_MC))
+    data = synth.accept_reject(
+        W.n_data, lambda x, y: oracle.intensity((x, y), W, W.theta_true),
+        synth.rng_for(0, synth.configs.STREAM_DATA), scan=200_000, batch=1 << 16)
+    rng = synth.rng_for(0, synth.configs.STREAM_TEST)
+    th0 = W.theta_true + rng.normal(scale=[0.1, 0.1, 0.01, 0.01] * 2)
+    ref = oracle.newton_cg_fit(data, mc, W, th0, xtol=1e-8)
+    return W, data, mc, th0, ref
+
+
+def _gauge(th):
+    c = th[0::4] + 1j * th[1::4]
+    c = c / c[0]
+    out = np.array(th, dtype=float).copy()
+    out[0::4], out[1::4] = c.real, c.imag
+    return out
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fit_matches_scipy_newton_cg(cfg0, prec):
+    W, data, mc, th0, ref = cfg0
+    say(f"[fit cfg0] hvp precision {prec}")
+    lik = likelihood(W, data, mc, streams=("f64", "f32"))
+    th, rep = lik.fit(th0, xtol=1e-8, hvp_precision=prec)
+    th = th.cpu().numpy()
+    say(f"  gpu nll {rep['nll']:.10f} iters {rep['iterations']} hvps {rep['n_hvp']} "
+        f"grads {rep['n_grad']} t {rep['seconds']:.3f}s; scipy nll {ref.fun:.10f} nit {ref.nit}")
+    assert rep["converged"] == 1
+    assert abs(rep["nll"] - ref.fun) <= 1e-6
+    assert abs(oracle.nll(data, mc, W, th) - ref.fun) <= 1e-6
+    np.testing.assert_allclose(_gauge(th)[2:], _gauge(ref.x)[2:], rtol=0, atol=2e-5)
+
+
+def test_fit_options(cfg0):
+    W, data, mc, th0, ref = cfg0
+    say("[fit options] time cap, free mask")
+    lik = likelihood(W, data, mc)
+    # a zero-length time budget stops at once with the start point
+    th, rep = lik.fit(th0, xtol=1e-8, time_cap_s=1e-9)
+    assert rep["code"] == -5 and rep["converged"] == 0
+    np.testing.assert_array_equal(th.cpu().numpy(), th0)
+    # fixed couplings of resonance 1 stay put; the fit still converges
+    mask = [0, 0, 1, 1, 1, 1, 1, 1]
+    th, rep = lik.fit(th0, xtol=1e-8, free_mask=mask)
+    th = th.cpu().numpy()
+    assert rep["converged"] == 1
+    np.testing.assert_array_equal(th[:2], th0[:2])
+    assert rep["nll"] <= ref.fun + 1e-6

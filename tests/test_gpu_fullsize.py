@@ -1,0 +1,119 @@
+"""Full-size checks on the GPU-scale workload (K = 12 over the three channels,
+1M data-like events, 5M uniform MC events) in the launch configuration the
+benchmark times: the NLL against the oracle over all 6M events, and the
+gradient and H v through properties that hold at any size (phase and scale
+invariance identities, central differences of the GPU NLL, the shard
+identity of eq. (4)-(7), bitwise repeatability)."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_cases import likelihood
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    W = synth.workload(1)
+    say("[fullsize] generating 1M + 5M events")
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(1, synth.configs.STREAM_MC))
+    data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
+                               synth.rng_for(1, synth.configs.STREAM_DATA))
+    lik = likelihood(W, data, mc, streams=("f64", "f32"))
+    return W, data, mc, lik
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def test_fullsize_nll_against_oracle(cfg1):
+    W, data, mc, lik = cfg1
+    say("[fullsize] NLL vs oracle over 6M events")
+    th = W.theta_true
+    ref = oracle.nll(data, mc, W, th)
+    hv, f, g = lik.hvp(th, np.ones(48))
+    assert abs(float(f) - ref) <= 1e-10 * abs(ref)
+    assert abs(float(lik.nll(th)) - ref) <= 1e-10 * abs(ref)
+    lik.set_precision("f32")
+    try:
+        assert abs(float(lik.nll(th)) - ref) <= 1e-5 * abs(ref)
+    finally:
+        lik.set_precision("f64")
+
+
+def test_fullsize_invariance_identities(cfg1):
+    """g . J theta = 0, H (J theta) = J g; g . Pi theta = 0, H (Pi theta) = -Pi g."""
+    W, data, mc, lik = cfg1
+    say("[fullsize] invariance identities")
+    th = W.theta_true + synth.rng_for(1, 3).normal(scale=0.01, size=48)
+    Jt = np.zeros(48)
+    Jt[0::4], Jt[1::4] = -th[1::4], th[0::4]
+    Pt = np.zeros(48)
+    Pt[0::4], Pt[1::4] = th[0::4], th[1::4]
+    hvJ, _, g = lik.hvp(th, Jt)
+    hvP, _, _ = lik.hvp(th, Pt)
+    g, hvJ, hvP = _np(g), _np(hvJ), _np(hvP)
+    Jg = np.zeros(48)
+    Jg[0::4], Jg[1::4] = -g[1::4], g[0::4]
+    Pg = np.zeros(48)
+    Pg[0::4], Pg[1::4] = g[0::4], g[1::4]
+    gmax = np.max(np.abs(g))
+    assert abs(g @ Jt) <= 1e-9 * gmax * np.abs(Jt).sum()
+    assert abs(g @ Pt) <= 1e-9 * gmax * np.abs(Pt).sum()
+    assert np.max(np.abs(hvJ - Jg)) <= 1e-9 * max(np.max(np.abs(hvJ)), gmax)
+    assert np.max(np.abs(hvP + Pg)) <= 1e-9 * max(np.max(np.abs(hvP)), gmax)
+
+
+def test_fullsize_central_differences(cfg1):
+    """Directional derivative of the GPU NLL (central difference, h = 1e-6)
+    equals g . d, and the difference of GPU gradients equals H d."""
+    W, data, mc, lik = cfg1
+    say("[fullsize] central differences")
+    th = W.theta_true
+    d = synth.rng_for(1, 4).normal(size=48)
+    h = 1e-6
+    hv, _, g = lik.hvp(th, d)
+    fp = float(lik.grad(th + h * d)[0])
+    fm = float(lik.grad(th - h * d)[0])
+    fd = (fp - fm) / (2 * h)
+    gd = float(_np(g) @ d)
+    assert abs(fd - gd) <= 1e-5 * np.abs(_np(g)).max() * np.abs(d).sum()
+    gp = _np(lik.grad(th + h * d)[1])
+    gm = _np(lik.grad(th - h * d)[1])
+    hfd = (gp - gm) / (2 * h)
+    assert np.max(np.abs(hfd - _np(hv))) <= 1e-4 * np.max(np.abs(_np(hv)))
+
+
+def test_fullsize_shards_and_determinism(cfg1):
+    W, data, mc, lik = cfg1
+    say("[fullsize] shard identity, determinism")
+    from paper_2403_09225_amd import combine
+    th = W.theta_true
+    v = synth.rng_for(1, 5).normal(size=48)
+    a = lik.hvp(th, v)
+    b = lik.hvp(th, v)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    hv0, f0, g0 = a
+    parts = []
+    for lo, hi in [(0, 2), (2, 4)]:
+        nd, nm = len(data[0]), len(mc[0])
+        d = (data[0][lo * nd // 4:hi * nd // 4], data[1][lo * nd // 4:hi * nd // 4])
+        m = (mc[0][lo * nm // 4:hi * nm // 4], mc[1][lo * nm // 4:hi * nm // 4])
+        parts.append(likelihood(W, d, m).partials(th, v))
+    f1, g1, hv1 = combine(parts, 48, len(data[0]), len(mc[0]), v)
+    assert float(f1) == pytest.approx(float(f0), rel=1e-13)
+    gs = np.max(np.abs(_np(g0)))
+    assert np.max(np.abs(_np(g1) - _np(g0))) <= 1e-11 * gs
+    assert np.max(np.abs(_np(hv1) - _np(hv0))) <= 1e-11 * np.max(np.abs(_np(hv0)))
