@@ -70,7 +70,7 @@ Layout layout_of(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
   L.tbl64 = take(sizeof(double) * KPAD * TS);
   L.tbl32 = take(sizeof(float) * KPAD * TS);
   L.itbl = take(sizeof(int) * KPAD * ITS);
-  L.part = take(sizeof(double) * 2 * (size_t)MAX_BLOCKS * (1 + 8 * (size_t)K));
+  L.part = take(sizeof(double) * 2 * (size_t)MAX_BLOCKS * (1 + NMOM_HVP * (size_t)K));
   L.dd = take(sizeof(double) * 2 * (2 + 4 * (size_t)P));
   L.scratch = take(sizeof(double) * (8 * (size_t)P + 16));
   L.stride = (int64_t)align_up((size_t)(n_data + n_mc), 64);
@@ -83,8 +83,8 @@ Layout layout_of(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
 bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
 // Shape index within the built list (for the grid cache).
-const int kShapes[][2] = {{1, 2}, {1, 4}, {1, 8}, {1, 12}, {2, 4}, {2, 6}, {4, 2},
-                          {4, 3}, {4, 4}, {8, 2}, {8, 4}, {8, 8}, {16, 4}};
+const int kShapes[][2] = {{1, 2}, {1, 4}, {2, 4}, {4, 2}, {4, 3}, {4, 4},
+                          {8, 2}, {8, 4}, {16, 2}, {16, 4}, {32, 2}};
 const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 int shape_index(int T, int R) {
@@ -99,11 +99,11 @@ int shape_index(int T, int R) {
 void auto_shape(int K, int& T, int& R) {
   if (K <= 2) { T = 1; R = 2; return; }
   if (K <= 4) { T = 1; R = 4; return; }
-  if (K <= 8) { T = 2; R = 4; return; }
+  if (K <= 8) { T = 4; R = 2; return; }
   if (K <= 12) { T = 4; R = 3; return; }
-  if (K <= 16) { T = 4; R = 4; return; }
-  if (K <= 32) { T = 8; R = 4; return; }
-  T = 16; R = 4;
+  if (K <= 16) { T = 8; R = 2; return; }
+  if (K <= 32) { T = 16; R = 2; return; }
+  T = 32; R = 2;
 }
 
 void shape_of(const pwa_ctx* c, int& T, int& R) {
@@ -116,14 +116,14 @@ void shape_of(const pwa_ctx* c, int& T, int& R) {
 }
 
 int grid_blocks(pwa_ctx* c, int prec, int mode, int T, int R) {
-  const int si = (mode == MODE_NLL) ? 0 : shape_index(T, R);
+  const int si = shape_index(T, R);
   int& cached = c->grid_cache[prec][mode][si < 0 ? 0 : si];
   if (cached == 0) {
     int occ = eval_occupancy(prec, mode, T, R);
     if (occ <= 0) occ = 1;
     cached = std::max(1, std::min(MAX_BLOCKS, c->cu_count * occ));
   }
-  const int teams = (mode == MODE_NLL) ? BLOCK : BLOCK / T;
+  const int teams = BLOCK / T;
   const int64_t n = c->n_data + c->n_mc;
   const int64_t need = std::max<int64_t>(2, (n + teams - 1) / teams);
   return (int)std::min<int64_t>(cached, need);
@@ -162,8 +162,8 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
              const double* d_v, double* d_nll, double* d_grad, double* d_hv, double* d_dd,
              hipStream_t st) {
   int T = 1, R = 1;
-  if (mode != MODE_NLL) shape_of(c, T, R);
-  const int kslots = (mode == MODE_NLL) ? c->K : T * R;
+  shape_of(c, T, R);
+  const int kslots = T * R;
   hipError_t e = launch_table(d_theta, d_v, c->md, kslots, c->tbl64, c->tbl32, c->itbl, c->status, st);
   if (e != hipSuccess) return PWA_E_HIP;
   const int nb = grid_blocks(c, prec, mode, T, R);
@@ -193,7 +193,8 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
   f.part = c->part;
   f.nb_data = a.nb_data;
   f.nb_mc = a.nb_mc;
-  f.V = 1 + (mode >= MODE_GRAD ? 4 * c->K : 0) + (mode == MODE_HVP ? 4 * c->K : 0);
+  f.V = 1 + (mode == MODE_HVP ? NMOM_HVP : (mode == MODE_GRAD ? NMOM_GRAD : 0)) * c->K;
+  f.tbl = c->tbl64;
   f.K = c->K;
   f.mode = mode;
   f.out_kind = out_kind;

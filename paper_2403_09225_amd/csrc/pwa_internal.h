@@ -16,32 +16,48 @@ namespace pwa {
 // and the per-resonance functions of M only
 //   eta(M) = M^2 / (q0^(2J+1) F_J(z0)^2),  beta(M) = 1/F_J(z0),
 // one has M Gamma(s) = Gamma eta g, and the amplitude is
-//   a = beta u / D,  D = (M^2 - s) - i Gamma eta g.
-// Entries are laid out in the order the kernel consumes them.
+//   a = beta u w,  w = 1/D,  D = (M^2 - s) - i Gamma eta g.
+// The first slots are read per event by the pass kernels; the rest only by
+// the finaliser, which contracts the event moments with them.
 enum TableSlot : int {
   TB_M2 = 0,      // M^2
   TB_NGE = 1,     // -Gamma eta           (Im D = TB_NGE * g)
-  TB_BETA = 2,    // beta
-  TB_CR = 3,      // Re c
-  TB_CI = 4,      // Im c
-  TB_UMUL = 5,    // u = u_plane * UMUL + UADD (J = 0: u = 1)
-  TB_UADD = 6,
-  TB_DDR = 7,     // directional derivative of D along v: (DDR, DDIG * g)
-  TB_DDIG = 8,
-  TB_BDOT = 9,    // v_M beta'
-  TB_VR = 10,     // v on Re c, Im c
-  TB_VI = 11,
-  TB_2M = 12,     // dD/dM = (2M, NGE1 * g)
-  TB_NGE1 = 13,   // -Gamma eta'
-  TB_NETA = 14,   // dD/dGamma = (0, NETA * g), NETA = -eta
-  TB_BETA1 = 15,  // beta'
-  TB_DMDDR = 16,  // d/dM of the directional derivative: (DMDDR, DMDDIG * g)
-  TB_DMDDIG = 17,
-  TB_DGDDIG = 18, // d/dGamma of the directional derivative: (0, DGDDIG * g)
-  TB_BDOT1 = 19,  // v_M beta''
-  TB_USED = 20
+  TB_UMUL = 2,    // u = u_plane * UMUL + UADD (J = 0: u = 1)
+  TB_UADD = 3,
+  TB_CBR = 4,     // c beta               (z = sum c beta u w)
+  TB_CBI = 5,
+  TB_K1R = 6,     // zdot = sum K1 u w + K2 u w^2 + K3 u g w^2
+  TB_K1I = 7,
+  TB_K2R = 8,
+  TB_K2I = 9,
+  TB_K3R = 10,
+  TB_K3I = 11,
+  TB_HOT = 12,    // slots read by the pass kernels
+  TB_BETA = 12,   // beta, beta'
+  TB_BETA1 = 13,
+  TB_BDOT = 14,   // v_M beta', v_M beta''
+  TB_BDOT1 = 15,
+  TB_CR = 16,     // c
+  TB_CI = 17,
+  TB_VR = 18,     // v on Re c, Im c, M
+  TB_VI = 19,
+  TB_VM = 20,
+  TB_2M = 21,     // dD/dM = (2M, NGE1 g)
+  TB_NGE1 = 22,
+  TB_NETA = 23,   // dD/dGamma = (0, NETA g), NETA = -eta
+  TB_DDR = 24,    // directional derivative of D along v: (DDR, DDIG g)
+  TB_DDIG = 25,
+  TB_DMDDIG = 26, // its M-derivative: (2 v_M, DMDDIG g)
+  TB_DGDDIG = 27, // its Gamma-derivative: (0, DGDDIG g)
+  TB_USED = 28
 };
-constexpr int TS = 24;        // table stride (reals) per resonance
+// Event moments accumulated per resonance (complex, re/im interleaved):
+//   C1..C3 = sum gamma u {w, w^2, g w^2}           (gradient and HVP)
+//   B1..B3 = sum alpha u {w, w^2, g w^2}           (HVP)
+//   C4..C6 = sum gamma u {w^3, g w^3, g^2 w^3}     (HVP)
+constexpr int NMOM_GRAD = 6;
+constexpr int NMOM_HVP = 18;
+constexpr int TS = 32;        // table stride (reals) per resonance
 constexpr int ITS = 4;        // int table stride: s plane, u plane, g plane, J
 constexpr int KPAD = 64;      // table rows (resonance slots incl. padding)
 constexpr int BLOCK = 256;    // threads per block of the evaluation kernels
@@ -88,8 +104,9 @@ struct EvalArgs {
 
 struct FinalArgs {
   const double* part;
+  const double* tbl;         // resonance table (finaliser slots)
   int nb_data, nb_mc;
-  int V;                     // values per block: 1 (+4K) (+4K)
+  int V;                     // values per block: 1 + NMOM * K
   int K, mode, out_kind;
   double n_data, n_mc;
   const double* v;           // direction (HVP), may be null

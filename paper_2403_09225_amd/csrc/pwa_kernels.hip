@@ -13,9 +13,9 @@
 //   1. table_kernel: per-resonance constants from (theta, v), including the
 //      first and second M-derivatives of the mass-only factors, by
 //      second-order Taylor arithmetic in one thread per resonance.
-//   2. eval_kernel / nll_kernel: one pass over the events.  A team of T lanes
-//      shares an event; each lane owns R resonances and keeps their gradient
-//      and HVP sums in FP64 registers over all the events it visits.  Event
+//   2. eval_kernel: one pass over the events.  A team of T lanes shares an
+//      event; each lane owns R resonances and keeps their event moments in
+//      FP64 registers over all the events it visits.  Event
 //      sums are reduced per wave with a double-double butterfly and per block
 //      in a fixed order into per-block (hi, lo) partials: no atomics, so the
 //      result is bitwise reproducible for a given grid.
@@ -60,6 +60,13 @@ __device__ __forceinline__ double rcp_r(double x) {
 }
 __device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double log_r(double x) { return log(x); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
+// FP64 accumulation of per-event terms (converted once for the FP32 path).
+__device__ __forceinline__ void acc_add(double& acc, double x) { acc += x; }
+__device__ __forceinline__ void acc_add(double& acc, float x) { acc += (double)x; }
+__device__ __forceinline__ void acc_fma(double& acc, double a, double b) { acc = fma(a, b, acc); }
+__device__ __forceinline__ void acc_fma(double& acc, float a, float b) { acc += (double)(a * b); }
 __device__ __forceinline__ float log_r(float x) { return __logf(x); }
 
 // Double-double accumulation (TwoSum then renormalise).  Symmetric in its
@@ -210,32 +217,44 @@ __global__ __launch_bounds__(64) void table_kernel(const double* __restrict__ th
       } else {
         eta = Mj;
       }
+      const double Ddr = 2.0 * M * vM;
+      const double Ddig = -(vM * G * eta.d + vG * eta.v);
+      const double bdot = vM * beta.d;
+      const double cbr = cr * beta.v, cbi = ci * beta.v;
       e[TB_M2] = M * M;
       e[TB_NGE] = -G * eta.v;
-      e[TB_BETA] = beta.v;
-      e[TB_CR] = cr;
-      e[TB_CI] = ci;
       e[TB_UMUL] = (J == 0) ? 0.0 : 1.0;
       e[TB_UADD] = (J == 0) ? 1.0 : 0.0;
-      e[TB_DDR] = 2.0 * M * vM;
-      e[TB_DDIG] = -(vM * G * eta.d + vG * eta.v);
-      e[TB_BDOT] = vM * beta.d;
+      e[TB_CBR] = cbr;
+      e[TB_CBI] = cbi;
+      e[TB_K1R] = vr * beta.v + cr * bdot;   // cdot beta + c beta'v_M
+      e[TB_K1I] = vi * beta.v + ci * bdot;
+      e[TB_K2R] = -cbr * Ddr;                // -c beta Ddr
+      e[TB_K2I] = -cbi * Ddr;
+      e[TB_K3R] = cbi * Ddig;                // -i c beta Ddig
+      e[TB_K3I] = -cbr * Ddig;
+      e[TB_BETA] = beta.v;
+      e[TB_BETA1] = beta.d;
+      e[TB_BDOT] = bdot;
+      e[TB_BDOT1] = vM * beta.dd;
+      e[TB_CR] = cr;
+      e[TB_CI] = ci;
       e[TB_VR] = vr;
       e[TB_VI] = vi;
+      e[TB_VM] = vM;
       e[TB_2M] = 2.0 * M;
       e[TB_NGE1] = -G * eta.d;
       e[TB_NETA] = -eta.v;
-      e[TB_BETA1] = beta.d;
-      e[TB_DMDDR] = 2.0 * vM;
+      e[TB_DDR] = Ddr;
+      e[TB_DDIG] = Ddig;
       e[TB_DMDDIG] = -(vM * G * eta.dd + vG * eta.d);
       e[TB_DGDDIG] = -vM * eta.d;
-      e[TB_BDOT1] = vM * beta.dd;
       f[0] = md.fidx[k][0];
       f[1] = md.fidx[k][1];
       f[2] = md.fidx[k][2];
       f[3] = J;
     } else {
-      // inert padding slot: a = 0 and every derivative 0, D = -1 - s != 0
+      // inert padding slot: c = v = 0 so it adds nothing; D = -1 - s != 0
       e[TB_M2] = -1.0;
       e[TB_UADD] = 1.0;
       f[0] = f[1] = f[2] = f[3] = 0;
@@ -276,82 +295,31 @@ __device__ __forceinline__ Range block_range(const EvalArgs& a) {
 }
 
 // ------------------------------------------------------------------------
-// NLL-only pass: one lane per event, runtime resonance loop, table in SGPRs.
-// ------------------------------------------------------------------------
-template <typename Real>
-__global__ __launch_bounds__(BLOCK) void nll_kernel(EvalArgs a) {
-  typedef typename CPtr<Real>::type CReal;
-  const Range rg = block_range(a);
-  const Real* __restrict__ planes = (const Real*)a.planes;
-  const int64_t stride = a.stride;
-  const Real* tsrc = (sizeof(Real) == 8) ? (const Real*)a.tbl64 : (const Real*)a.tbl32;
-  double acc = 0.0;
-  for (int64_t e0 = rg.begin; e0 < rg.end; e0 += BLOCK) {
-    const int64_t e = e0 + threadIdx.x;
-    const bool valid = e < rg.end;
-    const int64_t ev = rg.base + (valid ? e : rg.begin);
-    CReal* tb = opaque_s((CReal*)tsrc);
-    c_int* it = opaque_s((c_int*)a.itbl);
-    Real zr = 0, zi = 0;
-    for (int k = 0; k < a.K; ++k) {
-      CReal* t = tb + k * TS;
-      const Real s = planes[it[k * ITS + 0] * stride + ev];
-      const Real u = planes[it[k * ITS + 1] * stride + ev] * t[TB_UMUL] + t[TB_UADD];
-      const Real g = planes[it[k * ITS + 2] * stride + ev];
-      const Real Dr = t[TB_M2] - s;
-      const Real Di = t[TB_NGE] * g;
-      const Real inv = rcp_r(Dr * Dr + Di * Di);
-      const Real bu = t[TB_BETA] * u * inv;
-      const Real ar = bu * Dr, ai = -bu * Di;
-      zr += t[TB_CR] * ar - t[TB_CI] * ai;
-      zi += t[TB_CR] * ai + t[TB_CI] * ar;
-    }
-    const Real om = zr * zr + zi * zi;
-    const double term = rg.is_data ? (double)log_r(om) : (double)om;
-    acc += valid ? term : 0.0;
-  }
-  double hi = acc, lo = 0.0;
-  dd_wave_reduce(hi, lo, 1);
-  __shared__ double red[BLOCK / 64][2];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[wave][0] = hi;
-    red[wave][1] = lo;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double h = red[0][0], l = red[0][1];
-    for (int w = 1; w < BLOCK / 64; ++w) dd_add(h, l, red[w][0], red[w][1]);
-    a.part[blockIdx.x * 2 + 0] = h;
-    a.part[blockIdx.x * 2 + 1] = l;
-  }
-}
-
-// ------------------------------------------------------------------------
 // Gradient / HVP pass.
 //
-// Per event, with w = 1/D, w2 = w^2 and the directional derivative
-// Ddot = v_M dD/dM + v_Gamma dD/dGamma:
-//   a     = beta u w,            adot = u (beta' v_M w + beta wdot),  wdot = -Ddot w2
-//   da/dM = u (beta' w + beta wM),  wM = -(dD/dM) w2
-//   da/dG = beta u wG,              wG = -(dD/dGamma) w2
-//   z = sum c a,  zdot = sum (cdot a + c adot)           (zdot = dz along v)
-// The gradient of w = |z|^2 along theta_p is 2 Re(conj(z) dz/dtheta_p) and its
-// Hessian times v is 2 Re(conj(zdot) dz/dtheta_p + conj(z) dzdot/dtheta_p).
-// For ln w (data) and w (MC) both are 2 Re(alpha dz/dtheta_p + gamma
-// dzdot/dtheta_p) with per-event weights
-//   data: gamma = conj(z)/w, alpha = (conj(zdot) - (wdot/w) conj(z))/w
-//   MC:   gamma = conj(z),   alpha = conj(zdot)
-// (the gradient uses gamma only).  The factor 2 is applied by the finaliser.
+// Per event and resonance, with w = 1/D and the per-event weights
+//   data: gamma = conj(z)/|z|^2, alpha = (conj(zdot) - (2 Re(conj(z) zdot)/|z|^2) conj(z))/|z|^2
+//   MC:   gamma = conj(z),       alpha = conj(zdot)
+// (zdot = dz along v), every gradient and HVP component is 2 Re of a linear
+// combination of the event moments
+//   C1..C6 = gamma u {w, w^2, g w^2, w^3, g w^3, g^2 w^3},
+//   B1..B3 = alpha u {w, w^2, g w^2},
+// with coefficients that depend on the resonance parameters only (the
+// derivatives of w = 1/D in M and Gamma are polynomials in w and g).  The
+// pass therefore accumulates these 9 complex moments per resonance in FP64
+// registers and the finaliser contracts them with the table.  The gradient
+// pass needs C1..C3 only.  z and zdot themselves are
+//   z = sum c beta u w,  zdot = sum K1 u w + K2 u w^2 + K3 u g w^2.
 // ------------------------------------------------------------------------
 template <typename Real, int MODE, int T, int R>
 __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
   static_assert(64 % T == 0, "team size must divide the wavefront");
   typedef typename CPtr<Real>::type CReal;
+  constexpr bool HVP = (MODE == MODE_HVP);
+  constexpr bool DER = (MODE != MODE_NLL);
   constexpr int TEAMS = BLOCK / T;
-  constexpr int NG = 4 * R;
-  constexpr int NH = (MODE == MODE_HVP) ? 4 * R : 0;
-  constexpr int NA = NG + NH;
+  constexpr int NM = HVP ? NMOM_HVP : (DER ? NMOM_GRAD : 0);
+  constexpr int NA = NM * R;
   constexpr int NV = 1 + NA;
   constexpr int NSLOT = T * R;
   constexpr int NWAVE = BLOCK / 64;
@@ -365,224 +333,293 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
   const int64_t stride = a.stride;
   const Real* tsrc = (sizeof(Real) == 8) ? (const Real*)a.tbl64 : (const Real*)a.tbl32;
 
-  __shared__ Real s_tb[(T > 1) ? NSLOT * TS : 1];
+  __shared__ Real s_tb[(T > 1) ? NSLOT * TB_HOT : 1];
   __shared__ int s_it[(T > 1) ? NSLOT * ITS : 1];
   if constexpr (T > 1) {
-    for (int i = tid; i < NSLOT * TS; i += BLOCK) s_tb[i] = tsrc[i];
+    for (int i = tid; i < NSLOT * TB_HOT; i += BLOCK) s_tb[i] = tsrc[(i / TB_HOT) * TS + i % TB_HOT];
     for (int i = tid; i < NSLOT * ITS; i += BLOCK) s_it[i] = a.itbl[i];
     __syncthreads();
   }
 
+  // Plane pointers of this lane's resonances (fixed for the whole kernel).
+  const Real* ps[R];
+  const Real* pu[R];
+  const Real* pg[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int is, iu, ig;
+    if constexpr (T == 1) {
+      is = a.itbl[r * ITS + 0];
+      iu = a.itbl[r * ITS + 1];
+      ig = a.itbl[r * ITS + 2];
+    } else {
+      is = s_it[(pos * R + r) * ITS + 0];
+      iu = s_it[(pos * R + r) * ITS + 1];
+      ig = s_it[(pos * R + r) * ITS + 2];
+    }
+    ps[r] = planes + (int64_t)is * stride;
+    pu[r] = planes + (int64_t)iu * stride;
+    pg[r] = planes + (int64_t)ig * stride;
+  }
+
   double accS = 0.0;
-  double acc[NA];
+  double acc[NA > 0 ? NA : 1];
 #pragma unroll
   for (int j = 0; j < NA; ++j) acc[j] = 0.0;
 
-  for (int64_t e0 = rg.begin; e0 < rg.end; e0 += TEAMS) {
-    const int64_t e = e0 + team;
-    const bool valid = e < rg.end;
-    const int64_t ev = rg.base + (valid ? e : rg.begin);
-
-    // Table access: scalar loads for T == 1, LDS rows of this lane otherwise.
-    CReal* tb = opaque_s((CReal*)tsrc);
-    c_int* it = opaque_s((c_int*)a.itbl);
-    const int row0 = (T > 1) ? opaque_v(pos * R) : 0;
-    auto TB = [&](int r, int slot) -> Real {
-      if constexpr (T == 1) return tb[r * TS + slot];
-      else return s_tb[(row0 + r) * TS + slot];
-    };
-    auto IT = [&](int r, int j) -> int {
-      if constexpr (T == 1) return it[r * ITS + j];
-      else return s_it[(row0 + r) * ITS + j];
-    };
-
-    // ---- pass 1: z (and zdot)
-    Real zr = 0, zi = 0, zdr = 0, zdi = 0;
+  if (rg.begin < rg.end) {
+    // Software pipeline: the stream values of the next event are loaded
+    // while the current one is computed.
+    Real sc[R], uc[R], gc[R];
+    {
+      const int64_t e = rg.begin + team;
+      const int64_t ev = rg.base + (e < rg.end ? e : rg.begin);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const Real s = planes[IT(r, 0) * stride + ev];
-      const Real u = planes[IT(r, 1) * stride + ev] * TB(r, TB_UMUL) + TB(r, TB_UADD);
-      const Real g = planes[IT(r, 2) * stride + ev];
-      const Real Dr = TB(r, TB_M2) - s;
-      const Real Di = TB(r, TB_NGE) * g;
-      const Real inv = rcp_r(Dr * Dr + Di * Di);
-      const Real wr = Dr * inv, wi = -Di * inv;
-      const Real beta = TB(r, TB_BETA);
-      const Real bu = beta * u;
-      const Real ar = bu * wr, ai = bu * wi;
-      const Real cr = TB(r, TB_CR), ci = TB(r, TB_CI);
-      zr += cr * ar - ci * ai;
-      zi += cr * ai + ci * ar;
-      if constexpr (MODE == MODE_HVP) {
-        const Real w2r = wr * wr - wi * wi, w2i = 2 * wr * wi;
-        const Real Ddr = TB(r, TB_DDR), Ddi = TB(r, TB_DDIG) * g;
-        const Real wdr = -(Ddr * w2r - Ddi * w2i), wdi = -(Ddr * w2i + Ddi * w2r);
-        const Real bdot = TB(r, TB_BDOT);
-        const Real adr = u * (bdot * wr + beta * wdr), adi = u * (bdot * wi + beta * wdi);
-        const Real vr = TB(r, TB_VR), vi = TB(r, TB_VI);
-        zdr += vr * ar - vi * ai + cr * adr - ci * adi;
-        zdi += vr * ai + vi * ar + cr * adi + ci * adr;
+      for (int r = 0; r < R; ++r) {
+        sc[r] = ps[r][ev];
+        uc[r] = pu[r][ev];
+        gc[r] = pg[r][ev];
       }
     }
-    if constexpr (T > 1) {
+    for (int64_t e0 = rg.begin; e0 < rg.end; e0 += TEAMS) {
+      const bool valid = e0 + team < rg.end;
+      Real sn[R], un[R], gn[R];
+      {
+        const int64_t en = e0 + TEAMS + team;
+        const int64_t evn = rg.base + (en < rg.end ? en : rg.begin);
 #pragma unroll
-      for (int off = 1; off < T; off <<= 1) {
-        zr += __shfl_xor(zr, off);
-        zi += __shfl_xor(zi, off);
-        if constexpr (MODE == MODE_HVP) {
-          zdr += __shfl_xor(zdr, off);
-          zdi += __shfl_xor(zdi, off);
+        for (int r = 0; r < R; ++r) {
+          sn[r] = ps[r][evn];
+          un[r] = pu[r][evn];
+          gn[r] = pg[r][evn];
+        }
+      }
+
+      // Table access: scalar loads for T == 1, this lane's LDS rows otherwise.
+      CReal* tb = opaque_s((CReal*)tsrc);
+      const int row0 = (T > 1) ? opaque_v(pos * R) : 0;
+      auto TB = [&](int r, int slot) -> Real {
+        if constexpr (T == 1) return tb[r * TS + slot];
+        else return s_tb[(row0 + r) * TB_HOT + slot];
+      };
+
+      // ---- pass 1: z (and zdot); keep w and u w of each resonance
+      Real cwr[R], cwi[R], cuwr[R], cuwi[R];
+      Real zr = 0, zi = 0, zdr = 0, zdi = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const Real s = sc[r];
+        const Real u = uc[r] * TB(r, TB_UMUL) + TB(r, TB_UADD);
+        const Real g = gc[r];
+        const Real Dr = TB(r, TB_M2) - s;
+        const Real Di = TB(r, TB_NGE) * g;
+        const Real inv = rcp_r(Dr * Dr + Di * Di);
+        const Real wr = Dr * inv, wi = -Di * inv;
+        const Real uwr = u * wr, uwi = u * wi;
+        const Real cbr = TB(r, TB_CBR), cbi = TB(r, TB_CBI);
+        zr = fma_r(cbr, uwr, fma_r(-cbi, uwi, zr));
+        zi = fma_r(cbr, uwi, fma_r(cbi, uwr, zi));
+        if constexpr (HVP) {
+          // zdot += K1 u w + (K2 + K3 g) u w^2
+          const Real uw2r = uwr * wr - uwi * wi, uw2i = uwr * wi + uwi * wr;
+          const Real kr = fma_r(TB(r, TB_K3R), g, TB(r, TB_K2R));
+          const Real ki = fma_r(TB(r, TB_K3I), g, TB(r, TB_K2I));
+          const Real k1r = TB(r, TB_K1R), k1i = TB(r, TB_K1I);
+          zdr = fma_r(k1r, uwr, fma_r(-k1i, uwi, fma_r(kr, uw2r, fma_r(-ki, uw2i, zdr))));
+          zdi = fma_r(k1r, uwi, fma_r(k1i, uwr, fma_r(kr, uw2i, fma_r(ki, uw2r, zdi))));
+        }
+        cwr[r] = wr;
+        cwi[r] = wi;
+        cuwr[r] = uwr;
+        cuwi[r] = uwi;
+      }
+      if constexpr (T > 1) {
+#pragma unroll
+        for (int off = 1; off < T; off <<= 1) {
+          zr += __shfl_xor(zr, off);
+          zi += __shfl_xor(zi, off);
+          if constexpr (HVP) {
+            zdr += __shfl_xor(zdr, off);
+            zdi += __shfl_xor(zdi, off);
+          }
+        }
+      }
+
+      // ---- per-event weights
+      const Real om = zr * zr + zi * zi;
+      Real gr = 0, gi = 0, alr = 0, ali = 0;
+      double sterm;
+      if (rg.is_data) {
+        sterm = (double)log_r(om);
+        if constexpr (DER) {
+          const Real io = rcp_r(om);
+          gr = zr * io;
+          gi = -zi * io;
+          if constexpr (HVP) {
+            const Real t = 2 * (zr * zdr + zi * zdi) * io;
+            alr = (zdr - t * zr) * io;
+            ali = (t * zi - zdi) * io;
+          }
+        }
+      } else {
+        sterm = (double)om;
+        gr = zr;
+        gi = -zi;
+        alr = zdr;
+        ali = -zdi;
+      }
+      if (!valid) {
+        sterm = 0.0;
+        gr = gi = alr = ali = 0;
+      }
+      if (pos == 0) accS += sterm;
+
+      // ---- pass 2: moments, as the chain p = x u w, q = p w, r = q w
+      // (x = gamma or alpha) so that C2 = sum q, C3 = sum g q, C4 = sum r, ...
+      if constexpr (DER) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const Real wr = cwr[r], wi = cwi[r], uwr = cuwr[r], uwi = cuwi[r], g = gc[r];
+          double* m = acc + NM * r;
+          const Real pr = gr * uwr - gi * uwi, pi = gr * uwi + gi * uwr;
+          const Real qr = pr * wr - pi * wi, qi = pr * wi + pi * wr;
+          acc_add(m[0], pr);
+          acc_add(m[1], pi);
+          acc_add(m[2], qr);
+          acc_add(m[3], qi);
+          acc_fma(m[4], g, qr);
+          acc_fma(m[5], g, qi);
+          if constexpr (HVP) {
+            const Real ar_ = alr * uwr - ali * uwi, ai_ = alr * uwi + ali * uwr;
+            const Real br_ = ar_ * wr - ai_ * wi, bi_ = ar_ * wi + ai_ * wr;
+            acc_add(m[6], ar_);
+            acc_add(m[7], ai_);
+            acc_add(m[8], br_);
+            acc_add(m[9], bi_);
+            acc_fma(m[10], g, br_);
+            acc_fma(m[11], g, bi_);
+            const Real rr = qr * wr - qi * wi, ri = qr * wi + qi * wr;
+            const Real g2 = g * g;
+            acc_add(m[12], rr);
+            acc_add(m[13], ri);
+            acc_fma(m[14], g, rr);
+            acc_fma(m[15], g, ri);
+            acc_fma(m[16], g2, rr);
+            acc_fma(m[17], g2, ri);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sc[r] = sn[r];
+        uc[r] = un[r];
+        gc[r] = gn[r];
+      }
+    }
+  }
+
+  // ---- reduction: wave butterfly over teams, then waves in fixed order,
+  // CH values per round to bound the LDS footprint.
+  // Block partial layout: [S, moments of resonance 0 (NM), resonance 1, ...].
+  constexpr int CH = 8;
+  __shared__ double red[NWAVE][T][CH][2];
+  const int K = a.K;
+  const int V = 1 + NM * K;
+  double* out = a.part + (int64_t)blockIdx.x * V * 2;
+#pragma unroll
+  for (int j0 = 0; j0 < NV; j0 += CH) {
+#pragma unroll
+    for (int jj = 0; jj < CH; ++jj) {
+      const int j = j0 + jj;
+      if (j < NV) {
+        double hi = (j == 0) ? accS : acc[j > 0 ? j - 1 : 0], lo = 0.0;
+        dd_wave_reduce(hi, lo, T);
+        if (lane < T) {
+          red[wave][lane][jj][0] = hi;
+          red[wave][lane][jj][1] = lo;
         }
       }
     }
-
-    // ---- per-event weights
-    const Real om = zr * zr + zi * zi;
-    Real gr, gi, alr = 0, ali = 0;
-    double sterm;
-    if (rg.is_data) {
-      sterm = (double)log_r(om);
-      const Real io = rcp_r(om);
-      gr = zr * io;
-      gi = -zi * io;
-      if constexpr (MODE == MODE_HVP) {
-        const Real t = 2 * (zr * zdr + zi * zdi) * io;
-        alr = (zdr - t * zr) * io;
-        ali = (t * zi - zdi) * io;
+    __syncthreads();
+    for (int idx = tid; idx < T * CH; idx += BLOCK) {
+      const int p = idx / CH, jj = idx % CH, j = j0 + jj;
+      if (j >= NV) continue;
+      int vi = -1;
+      if (j == 0) {
+        if (p == 0) vi = 0;
+      } else {
+        const int k = p * R + (j - 1) / NM;
+        if (k < K) vi = 1 + NM * k + (j - 1) % NM;
       }
-    } else {
-      sterm = (double)om;
-      gr = zr;
-      gi = -zi;
-      alr = zdr;
-      ali = -zdi;
+      if (vi < 0) continue;
+      double h = red[0][p][jj][0], l = red[0][p][jj][1];
+      for (int w = 1; w < NWAVE; ++w) dd_add(h, l, red[w][p][jj][0], red[w][p][jj][1]);
+      out[vi * 2 + 0] = h;
+      out[vi * 2 + 1] = l;
     }
-    if (!valid) {
-      sterm = 0.0;
-      gr = gi = alr = ali = 0;
-    }
-    if (pos == 0) accS += sterm;
-
-    // ---- pass 2: per-parameter sums
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const Real s = planes[IT(r, 0) * stride + ev];
-      const Real u = planes[IT(r, 1) * stride + ev] * TB(r, TB_UMUL) + TB(r, TB_UADD);
-      const Real g = planes[IT(r, 2) * stride + ev];
-      const Real Dr = TB(r, TB_M2) - s;
-      const Real Di = TB(r, TB_NGE) * g;
-      const Real inv = rcp_r(Dr * Dr + Di * Di);
-      const Real wr = Dr * inv, wi = -Di * inv;
-      const Real w2r = wr * wr - wi * wi, w2i = 2 * wr * wi;
-      const Real beta = TB(r, TB_BETA), beta1 = TB(r, TB_BETA1);
-      const Real bu = beta * u;
-      const Real ar = bu * wr, ai = bu * wi;
-      const Real cr = TB(r, TB_CR), ci = TB(r, TB_CI);
-      const Real dmr = TB(r, TB_2M), dmi = TB(r, TB_NGE1) * g;
-      const Real wMr = -(dmr * w2r - dmi * w2i), wMi = -(dmr * w2i + dmi * w2r);
-      const Real dgi = TB(r, TB_NETA) * g;
-      const Real wGr = dgi * w2i, wGi = -dgi * w2r;
-      const Real aMr = u * (beta1 * wr + beta * wMr), aMi = u * (beta1 * wi + beta * wMi);
-      const Real aGr = bu * wGr, aGi = bu * wGi;
-      const Real cMr = cr * aMr - ci * aMi, cMi = cr * aMi + ci * aMr;
-      const Real cGr = cr * aGr - ci * aGi, cGi = cr * aGi + ci * aGr;
-      acc[4 * r + 0] += (double)(gr * ar - gi * ai);
-      acc[4 * r + 1] += (double)(-(gr * ai + gi * ar));
-      acc[4 * r + 2] += (double)(gr * cMr - gi * cMi);
-      acc[4 * r + 3] += (double)(gr * cGr - gi * cGi);
-      if constexpr (MODE == MODE_HVP) {
-        const Real Ddr = TB(r, TB_DDR), Ddi = TB(r, TB_DDIG) * g;
-        const Real wdr = -(Ddr * w2r - Ddi * w2i), wdi = -(Ddr * w2i + Ddi * w2r);
-        const Real bdot = TB(r, TB_BDOT), bdot1 = TB(r, TB_BDOT1);
-        const Real adr = u * (bdot * wr + beta * wdr), adi = u * (bdot * wi + beta * wdi);
-        const Real wwMr = wr * wMr - wi * wMi, wwMi = wr * wMi + wi * wMr;
-        const Real e1r = TB(r, TB_DMDDR), e1i = TB(r, TB_DMDDIG) * g;
-        const Real wdMr = -(e1r * w2r - e1i * w2i) - 2 * (Ddr * wwMr - Ddi * wwMi);
-        const Real wdMi = -(e1r * w2i + e1i * w2r) - 2 * (Ddr * wwMi + Ddi * wwMr);
-        const Real wwGr = wr * wGr - wi * wGi, wwGi = wr * wGi + wi * wGr;
-        const Real e2i = TB(r, TB_DGDDIG) * g;
-        const Real wdGr = e2i * w2i - 2 * (Ddr * wwGr - Ddi * wwGi);
-        const Real wdGi = -e2i * w2r - 2 * (Ddr * wwGi + Ddi * wwGr);
-        const Real adMr = u * (bdot1 * wr + bdot * wMr + beta1 * wdr + beta * wdMr);
-        const Real adMi = u * (bdot1 * wi + bdot * wMi + beta1 * wdi + beta * wdMi);
-        const Real adGr = u * (bdot * wGr + beta * wdGr), adGi = u * (bdot * wGi + beta * wdGi);
-        const Real vr = TB(r, TB_VR), vi = TB(r, TB_VI);
-        const Real zMr = vr * aMr - vi * aMi + cr * adMr - ci * adMi;
-        const Real zMi = vr * aMi + vi * aMr + cr * adMi + ci * adMr;
-        const Real zGr = vr * aGr - vi * aGi + cr * adGr - ci * adGi;
-        const Real zGi = vr * aGi + vi * aGr + cr * adGi + ci * adGr;
-        acc[NG + 4 * r + 0] += (double)((alr * ar - ali * ai) + (gr * adr - gi * adi));
-        acc[NG + 4 * r + 1] += (double)(-(alr * ai + ali * ar) - (gr * adi + gi * adr));
-        acc[NG + 4 * r + 2] += (double)((alr * cMr - ali * cMi) + (gr * zMr - gi * zMi));
-        acc[NG + 4 * r + 3] += (double)((alr * cGr - ali * cGi) + (gr * zGr - gi * zGi));
-      }
-    }
-  }
-
-  // ---- reduction: wave butterfly over teams, then waves in fixed order
-  __shared__ double red[NWAVE][T][NV][2];
-  {
-    double hi = accS, lo = 0.0;
-    dd_wave_reduce(hi, lo, T);
-    if (lane < T) {
-      red[wave][lane][0][0] = hi;
-      red[wave][lane][0][1] = lo;
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < NA; ++j) {
-    double hi = acc[j], lo = 0.0;
-    dd_wave_reduce(hi, lo, T);
-    if (lane < T) {
-      red[wave][lane][1 + j][0] = hi;
-      red[wave][lane][1 + j][1] = lo;
-    }
-  }
-  __syncthreads();
-  const int K = a.K;
-  const int V = 1 + 4 * K + ((MODE == MODE_HVP) ? 4 * K : 0);
-  double* out = a.part + (int64_t)blockIdx.x * V * 2;
-  for (int idx = tid; idx < T * NV; idx += BLOCK) {
-    const int p = idx / NV, j = idx % NV;
-    int vi = -1;
-    if (j == 0) {
-      if (p == 0) vi = 0;
-    } else {
-      const int q = (j - 1) % NG;
-      const int k = p * R + q / 4;
-      if (k < K) vi = 1 + ((j - 1) >= NG ? 4 * K : 0) + 4 * k + (q % 4);
-    }
-    if (vi < 0) continue;
-    double h = red[0][p][j][0], l = red[0][p][j][1];
-    for (int w = 1; w < NWAVE; ++w) dd_add(h, l, red[w][p][j][0], red[w][p][j][1]);
-    out[vi * 2 + 0] = h;
-    out[vi * 2 + 1] = l;
+    __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------------
 // 3. Finaliser and combine (eq. (4), (6), (7) for NLL = -ln L).
-// Inputs are double-double totals; derivative totals still lack the factor 2
-// of d|z|^2 = 2 Re(conj(z) dz) when `halved` is set.
 // ------------------------------------------------------------------------
-struct Totals {
-  const double* F;   // dd pair
-  const double* G;   // dd pair
-  const double* dF;  // P dd pairs
-  const double* dG;
-  const double* HF;
-  const double* HG;
-  double scale;      // factor applied to derivative totals
+struct Cx {
+  double r, i;
 };
+__device__ __forceinline__ Cx cx(double r, double i) { return {r, i}; }
+__device__ __forceinline__ Cx operator+(Cx a, Cx b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ Cx operator*(Cx a, Cx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ Cx operator*(double s, Cx a) { return {s * a.r, s * a.i}; }
+__device__ __forceinline__ Cx mul_i(Cx a) { return {-a.i, a.r}; }
 
-__device__ void combine_block(const Totals& t, int P, int mode, double nd, double nm,
-                              const double* v, double* nll, double* grad, double* hv,
+// Contract the moments of one resonance (mom: C1,C2,C3[,B1,B2,B3,C4,C5,C6]
+// as doubles) with its table row: d/d(Re c, Im c, M, Gamma) of the event sum
+// and (HVP) its Hessian times v, both including the factor 2 of
+// d|z|^2 = 2 Re(conj(z) dz).
+__device__ void contract(const double* mom, const double* t, bool hvp, double* dg, double* dh) {
+  const Cx C1 = cx(mom[0], mom[1]), C2 = cx(mom[2], mom[3]), C3 = cx(mom[4], mom[5]);
+  const double be = t[TB_BETA], be1 = t[TB_BETA1], bd = t[TB_BDOT], bd1 = t[TB_BDOT1];
+  const Cx c = cx(t[TB_CR], t[TB_CI]), cd = cx(t[TB_VR], t[TB_VI]);
+  const double twoM = t[TB_2M], nge1 = t[TB_NGE1], neta = t[TB_NETA];
+  // dz/dM = c u (beta' w - beta (2M + i NGE1 g) w^2);  dz/dGamma = -i c beta NETA u g w^2
+  const Cx XM = be1 * C1 + (-twoM * be) * C2 + mul_i((-be * nge1) * C3);
+  const Cx XG = mul_i((-be * neta) * C3);
+  dg[0] = 2.0 * be * C1.r;
+  dg[1] = -2.0 * be * C1.i;
+  dg[2] = 2.0 * (c * XM).r;
+  dg[3] = 2.0 * (c * XG).r;
+  if (!hvp) return;
+  const Cx B1 = cx(mom[6], mom[7]), B2 = cx(mom[8], mom[9]), B3 = cx(mom[10], mom[11]);
+  const Cx C4 = cx(mom[12], mom[13]), C5 = cx(mom[14], mom[15]), C6 = cx(mom[16], mom[17]);
+  const double Ddr = t[TB_DDR], Ddig = t[TB_DDIG], dmd = t[TB_DMDDIG], dgd = t[TB_DGDDIG];
+  const double vM = t[TB_VM];
+  // Re c, Im c: alpha a + gamma adot
+  const Cx Y = be * B1 + bd * C1 + (-be * Ddr) * C2 + mul_i((-be * Ddig) * C3);
+  dh[0] = 2.0 * Y.r;
+  dh[1] = -2.0 * Y.i;
+  // M: alpha c aM + gamma (cdot aM + c adotM)
+  const Cx BM = be1 * B1 + (-twoM * be) * B2 + mul_i((-be * nge1) * B3);
+  const Cx ZM = bd1 * C1 + (-twoM * bd - be1 * Ddr - 2.0 * vM * be) * C2 +
+                mul_i((-(bd * nge1 + be1 * Ddig + be * dmd)) * C3) + (2.0 * twoM * be * Ddr) * C4 +
+                mul_i((2.0 * be * (Ddr * nge1 + twoM * Ddig)) * C5) + (-2.0 * be * Ddig * nge1) * C6;
+  dh[2] = 2.0 * (c * BM + cd * XM + c * ZM).r;
+  // Gamma: alpha c aG + gamma (cdot aG + c adotG)
+  const Cx BG = mul_i((-be * neta) * B3);
+  const Cx ZG = mul_i((-(bd * neta + be * dgd)) * C3) + mul_i((2.0 * be * neta * Ddr) * C5) +
+                (-2.0 * be * neta * Ddig) * C6;
+  dh[3] = 2.0 * (c * BG + cd * XG + c * ZG).r;
+}
+
+// Combine for one block: F, G (dd pairs), per-parameter derivative sums of
+// both sets (plain doubles), direction v.
+__device__ void combine_block(double F, double G, const double* dF, const double* dG,
+                              const double* HF, const double* HG, int P, int mode, double nd,
+                              double nm, const double* v, double* nll, double* grad, double* hv,
                               int* status) {
-  __shared__ double sc[3];
+  __shared__ double sc[2];
   const int tid = threadIdx.x;
   if (tid == 0) {
-    const double F = t.F[0] + t.F[1];
-    const double G = t.G[0] + t.G[1];
     double val = -F + nd * log(G / nm);
     int flags = status ? status[0] : 0;
     if (!(G > 0.0) || !isfinite(val)) flags |= 2;
@@ -590,14 +627,11 @@ __device__ void combine_block(const Totals& t, int P, int mode, double nd, doubl
     double dh = 0.0, dl = 0.0;
     if (mode == MODE_HVP && v) {
       for (int p = 0; p < P; ++p) {
-        const double gp = t.scale * (t.dG[2 * p] + t.dG[2 * p + 1]);
-        const double prod = gp * v[p];
-        dd_add(dh, dl, prod, fma(gp, v[p], -prod));
+        const double prod = dG[p] * v[p];
+        dd_add(dh, dl, prod, fma(dG[p], v[p], -prod));
       }
     }
-    sc[0] = G;
-    sc[1] = dh + dl;
-    sc[2] = val;
+    sc[0] = dh + dl;
     if (nll) *nll = val;
     if (status) {
       status[0] = flags;
@@ -606,22 +640,17 @@ __device__ void combine_block(const Totals& t, int P, int mode, double nd, doubl
   }
   __syncthreads();
   if (mode == MODE_NLL) return;
-  const double G = sc[0], dGv = sc[1];
+  const double dGv = sc[0];
   const double wG = nd / G;
   for (int p = tid; p < P; p += blockDim.x) {
-    const double gF = t.scale * (t.dF[2 * p] + t.dF[2 * p + 1]);
-    const double gG = t.scale * (t.dG[2 * p] + t.dG[2 * p + 1]);
-    if (grad) grad[p] = -gF + wG * gG;
-    if (mode == MODE_HVP && hv) {
-      const double hF = t.scale * (t.HF[2 * p] + t.HF[2 * p + 1]);
-      const double hG = t.scale * (t.HG[2 * p] + t.HG[2 * p + 1]);
-      hv[p] = -hF + wG * hG - (wG / G) * gG * dGv;
-    }
+    if (grad) grad[p] = -dF[p] + wG * dG[p];
+    if (mode == MODE_HVP && hv) hv[p] = -HF[p] + wG * HG[p] - (wG / G) * dG[p] * dGv;
   }
 }
 
 __global__ __launch_bounds__(1024) void final_kernel(FinalArgs f) {
-  __shared__ double tot[2 * (1 + 8 * PWA_MAX_RES) * 2];
+  __shared__ double tot[2 * (1 + NMOM_HVP * PWA_MAX_RES) * 2];
+  __shared__ double der[4][4 * PWA_MAX_RES];   // dF, dG, HF, HG
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = blockDim.x >> 6;
   for (int vv = wave; vv < 2 * f.V; vv += nw) {
@@ -631,7 +660,8 @@ __global__ __launch_bounds__(1024) void final_kernel(FinalArgs f) {
     const int nb = set ? f.nb_mc : f.nb_data;
     double hi = 0.0, lo = 0.0;
     for (int b = lane; b < nb; b += 64)
-      dd_add(hi, lo, f.part[((int64_t)(b0 + b) * f.V + vi) * 2], f.part[((int64_t)(b0 + b) * f.V + vi) * 2 + 1]);
+      dd_add(hi, lo, f.part[((int64_t)(b0 + b) * f.V + vi) * 2],
+             f.part[((int64_t)(b0 + b) * f.V + vi) * 2 + 1]);
     dd_wave_reduce(hi, lo, 1);
     if (lane == 0) {
       tot[vv * 2] = hi;
@@ -640,28 +670,40 @@ __global__ __launch_bounds__(1024) void final_kernel(FinalArgs f) {
   }
   __syncthreads();
   const int K = f.K, P = 4 * K;
-  const double* D = tot;                 // data set values
-  const double* M = tot + 2 * f.V;       // MC set values
+  const bool hvp = f.mode == MODE_HVP;
+  const int NM = hvp ? NMOM_HVP : NMOM_GRAD;
+  if (f.mode != MODE_NLL) {
+    for (int q = tid; q < 2 * K; q += blockDim.x) {
+      const int set = q / K, k = q % K;
+      const double* src = tot + 2 * (set * f.V + 1 + NM * k);
+      double mom[NMOM_HVP];
+      for (int j = 0; j < NM; ++j) mom[j] = src[2 * j] + src[2 * j + 1];
+      double dg[4], dh[4] = {0.0, 0.0, 0.0, 0.0};
+      contract(mom, f.tbl + k * TS, hvp, dg, dh);
+      for (int j = 0; j < 4; ++j) {
+        der[set][4 * k + j] = dg[j];
+        der[2 + set][4 * k + j] = dh[j];
+      }
+    }
+  }
+  __syncthreads();
+  const double F = tot[0] + tot[1];
+  const double G = tot[2 * f.V] + tot[2 * f.V + 1];
   if (f.out_kind == OUT_PARTIALS) {
-    // [F, G, dF(P), dG(P), HFv(P), HGv(P)] as (hi, lo), derivatives x 2
+    // [F, G, dF(P), dG(P), HFv(P), HGv(P)] as (hi, lo) pairs
     const int NOUT = 2 + 4 * P;
     for (int i = tid; i < NOUT; i += blockDim.x) {
       double h = 0.0, l = 0.0;
       if (i == 0) {
-        h = D[0];
-        l = D[1];
+        h = tot[0];
+        l = tot[1];
       } else if (i == 1) {
-        h = M[0];
-        l = M[1];
+        h = tot[2 * f.V];
+        l = tot[2 * f.V + 1];
       } else {
         const int q = i - 2, grp = q / P, p = q % P;
-        const double* src = (grp % 2 == 0) ? D : M;
-        const int off = 1 + (grp >= 2 ? P : 0) + p;
-        const bool have = (grp < 2) ? (f.mode >= MODE_GRAD) : (f.mode == MODE_HVP);
-        if (have) {
-          h = 2.0 * src[2 * off];
-          l = 2.0 * src[2 * off + 1];
-        }
+        const bool have = (grp < 2) ? (f.mode >= MODE_GRAD) : hvp;
+        if (have) h = der[grp][p];
       }
       f.dd_out[2 * i] = h;
       f.dd_out[2 * i + 1] = l;
@@ -669,19 +711,12 @@ __global__ __launch_bounds__(1024) void final_kernel(FinalArgs f) {
     if (tid == 0 && f.status && f.status[0]) atomicOr(&f.status[1], f.status[0]);
     return;
   }
-  Totals t;
-  t.F = D;
-  t.G = M;
-  t.dF = D + 2;
-  t.dG = M + 2;
-  t.HF = D + 2 + 2 * P;
-  t.HG = M + 2 + 2 * P;
-  t.scale = 2.0;
-  combine_block(t, P, f.mode, f.n_data, f.n_mc, f.v, f.nll, f.grad, f.hv, f.status);
+  combine_block(F, G, der[0], der[1], der[2], der[3], P, f.mode, f.n_data, f.n_mc, f.v, f.nll,
+                f.grad, f.hv, f.status);
 }
 
-// pwa_combine: shard partials [F, G, dF, dG, HF, HG] (dd pairs, already
-// including the factor 2), summed over shards in index order.
+// pwa_combine: shard partials [F, G, dF, dG, HF, HG] (dd pairs), summed over
+// shards in index order.
 __global__ __launch_bounds__(1024) void combine_kernel(int P, int n_shards,
                                                        const double* __restrict__ parts,
                                                        double nd, double nm,
@@ -689,6 +724,7 @@ __global__ __launch_bounds__(1024) void combine_kernel(int P, int n_shards,
                                                        double* nll, double* grad, double* hv,
                                                        int* status) {
   __shared__ double tot[(2 + 4 * 4 * PWA_MAX_RES) * 2];
+  __shared__ double flat[2 + 4 * 4 * PWA_MAX_RES];
   const int NOUT = 2 + 4 * P;
   for (int i = threadIdx.x; i < NOUT; i += blockDim.x) {
     double h = 0.0, l = 0.0;
@@ -696,20 +732,13 @@ __global__ __launch_bounds__(1024) void combine_kernel(int P, int n_shards,
       dd_add(h, l, parts[((int64_t)s * NOUT + i) * 2], parts[((int64_t)s * NOUT + i) * 2 + 1]);
     tot[2 * i] = h;
     tot[2 * i + 1] = l;
+    flat[i] = h + l;
   }
-  __syncthreads();
-  Totals t;
-  t.F = tot;
-  t.G = tot + 2;
-  t.dF = tot + 4;
-  t.dG = tot + 4 + 2 * P;
-  t.HF = tot + 4 + 4 * P;
-  t.HG = tot + 4 + 6 * P;
-  t.scale = 1.0;
   if (threadIdx.x == 0 && status) status[0] = 0;
   __syncthreads();
-  combine_block(t, P, hv ? MODE_HVP : (grad ? MODE_GRAD : MODE_NLL), nd, nm, v, nll, grad, hv,
-                status);
+  combine_block(tot[0] + tot[1], tot[2] + tot[3], flat + 2, flat + 2 + P, flat + 2 + 2 * P,
+                flat + 2 + 3 * P, P, hv ? MODE_HVP : (grad ? MODE_GRAD : MODE_NLL), nd, nm, v,
+                nll, grad, hv, status);
 }
 
 // ------------------------------------------------------------------------
@@ -738,7 +767,7 @@ hipError_t launch_table(const double* theta, const double* v, const ModelDev& md
 
 // Launch shapes (lanes per event T, resonances per lane R) that are built.
 #define PWA_SHAPES(X) \
-  X(1, 2) X(1, 4) X(1, 8) X(1, 12) X(2, 4) X(2, 6) X(4, 2) X(4, 3) X(4, 4) X(8, 2) X(8, 4) X(8, 8) X(16, 4)
+  X(1, 2) X(1, 4) X(2, 4) X(4, 2) X(4, 3) X(4, 4) X(8, 2) X(8, 4) X(16, 2) X(16, 4) X(32, 2)
 
 bool shape_built(int T, int R) {
 #define PWA_IS(TT, RR) if (T == TT && R == RR) return true;
@@ -750,9 +779,10 @@ bool shape_built(int T, int R) {
 typedef void (*EvalFn)(EvalArgs);
 
 static EvalFn eval_fn(int is_f32, int mode, int T, int R) {
-  if (mode == MODE_NLL) return is_f32 ? nll_kernel<float> : nll_kernel<double>;
 #define PWA_PICK(TT, RR)                                                              \
   if (T == TT && R == RR) {                                                           \
+    if (mode == MODE_NLL)                                                             \
+      return is_f32 ? eval_kernel<float, MODE_NLL, TT, RR> : eval_kernel<double, MODE_NLL, TT, RR>;   \
     if (mode == MODE_GRAD)                                                            \
       return is_f32 ? eval_kernel<float, MODE_GRAD, TT, RR> : eval_kernel<double, MODE_GRAD, TT, RR>; \
     return is_f32 ? eval_kernel<float, MODE_HVP, TT, RR> : eval_kernel<double, MODE_HVP, TT, RR>;     \

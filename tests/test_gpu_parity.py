@@ -52,7 +52,7 @@ def test_fp64_parity(K, nd, nm, seed, wm):
     _check_fp64(lik, model, th, data, mc, v)
 
 
-@pytest.mark.parametrize("shape", [(1, 12), (2, 6), (4, 3), (4, 4), (8, 2), (8, 4), (8, 8), (16, 4)])
+@pytest.mark.parametrize("shape", [(4, 3), (4, 4), (8, 2), (8, 4), (16, 2), (16, 4), (32, 2)])
 def test_every_launch_shape(shape):
     say(f"[shape] K=12 T,R={shape}")
     model, th, data, mc, v = case(12, 1777, 6001, 20)
@@ -61,8 +61,8 @@ def test_every_launch_shape(shape):
     _check_fp64(lik, model, th, data, mc, v)
 
 
-@pytest.mark.parametrize("K,shape", [(2, (1, 2)), (2, (1, 4)), (3, (1, 4)), (8, (1, 8)),
-                                     (8, (2, 4)), (6, (4, 2)), (16, (4, 4)), (30, (16, 4))])
+@pytest.mark.parametrize("K,shape", [(2, (1, 2)), (2, (1, 4)), (3, (1, 4)), (8, (2, 4)),
+                                     (6, (4, 2)), (16, (4, 4)), (30, (16, 2)), (64, (32, 2))])
 def test_small_k_shapes(K, shape):
     say(f"[shape] K={K} T,R={shape}")
     model, th, data, mc, v = case(K, 913, 3007, 21 + K)
