@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--shape", default="", help="lanes_per_event,res_per_lane override")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the likelihood on a single MI355X "
@@ -165,6 +167,14 @@ def main():
                    "launch_shape": args.shape or "auto", "grid_blocks": lik.grid_blocks()},
         "roofline": roof,
     }
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes_each_way"] = src.numel() * 8
+        del src, dst
     if not args.no_fit:
         result["newton_cg_time_to_min"] = fit_compare(lik, W)
         print("[bench] fits done", file=sys.stderr, flush=True)

@@ -211,11 +211,13 @@ const char* pwa_status_str(int status);
 /* Number of parameters P = 4K of a context (or -1 for null). */
 int32_t pwa_n_par(const pwa_ctx* ctx);
 
-/* Kernel launch shape of the NLL/gradient/HVP kernels: `lanes_per_event`
- * lanes cooperate on one event, each owning `res_per_lane` resonances
- * (lanes_per_event * res_per_lane >= K).  0, 0 restores the automatic choice.
- * PWA_E_INVALID for a shape that is not built. */
-int pwa_set_launch_shape(pwa_ctx* ctx, int32_t lanes_per_event, int32_t res_per_lane);
+/* Launch shape of the NLL/gradient/HVP pass kernels (for tuning; the
+ * default is an automatic choice by K).  layout 1: `groups` lanes of one
+ * wavefront cooperate on each event; layout 2: `groups` wavefronts of one
+ * block cooperate on each batch of 64 events.  Each lane owns `res_per_group`
+ * resonances; groups * res_per_group >= K.  layout 0 restores the automatic
+ * choice.  PWA_E_INVALID for a shape that is not built. */
+int pwa_set_launch_shape(pwa_ctx* ctx, int32_t layout, int32_t groups, int32_t res_per_group);
 
 /* Number of thread blocks the NLL/gradient/HVP kernels launch (after
  * pwa_bind), or -1. */
@@ -231,6 +233,50 @@ int32_t pwa_grid_blocks(const pwa_ctx* ctx);
  * PWA_E_HIP. */
 int pwa_set_kernel_timing(pwa_ctx* ctx, int32_t enable);
 int pwa_kernel_time(pwa_ctx* ctx, double* total_ms, int64_t* n_launches);
+
+/* ---------------------------------------------------------------------------
+ * Fixed-lineshape batched path.  With the masses and widths frozen, the
+ * amplitudes a_k(x) of eq. (1) are fixed and the couplings enter linearly:
+ * for a batch of coupling vectors c_b the data term is
+ * F_b = sum_data ln |sum_k c_kb a_k(x)|^2 (a complex matrix product of the
+ * N_D x K amplitude matrix with the K x B coupling block, then a log), and the
+ * normalisation is G_b = c_b^H Gm c_b with the K x K Gram matrix
+ * Gm = sum_MC conj(a_k) a_l.  NLL_b = -F_b + N_D ln(G_b / N_MC) (eq. (3)).
+ * ------------------------------------------------------------------------- */
+typedef enum pwa_operand {
+  PWA_OP_F64 = 0,   /* FP64 operands, FP64 matrix-core accumulation          */
+  PWA_OP_F32 = 1,   /* FP32 operands, FP32 accumulation                      */
+  PWA_OP_BF16 = 2,  /* BF16 operands, FP32 accumulation                      */
+  PWA_OP_F16 = 3,   /* FP16 operands, FP32 accumulation                      */
+  PWA_OP_F16X3 = 4  /* FP16 hi + lo split of both operands, three products
+                       (hi*hi + hi*lo + lo*hi), FP32 accumulation            */
+} pwa_operand;
+
+/* Device workspace (bytes) of the batched path for n_data data events,
+ * operand format `operand` and up to max_batch coupling vectors per call.
+ * 0 on invalid arguments (K > 24 is not supported on this path). */
+size_t pwa_batched_workspace_bytes(const pwa_ctx* ctx, int64_t n_data, int32_t operand,
+                                   int32_t max_batch);
+
+/* Freeze M and Gamma at d_theta (P doubles; the couplings in it are ignored):
+ * builds the data amplitude matrix in the operand format and the FP64 Gram
+ * matrix of the MC amplitudes (matrix cores, FP64) in d_bws, a caller-owned
+ * 256-byte aligned device buffer of bws_bytes >= pwa_batched_workspace_bytes.
+ * Needs a bound context with the FP64 event stream.
+ * Errors: PWA_E_STATE, PWA_E_INVALID, PWA_E_WORKSPACE, PWA_E_HIP. */
+int pwa_freeze(pwa_ctx* ctx, const double* d_theta, int32_t operand, int32_t max_batch,
+               void* d_bws, size_t bws_bytes, hipStream_t stream);
+
+/* NLL of B coupling vectors at the frozen masses and widths.  d_C: K x B
+ * complex couplings as (re, im) FP64 pairs, start-major: coupling k of
+ * start b at d_C[2 (b K + k)], d_C[2 (b K + k) + 1].  d_nll: B doubles
+ * (+inf where G_b <= 0).  B <= max_batch of pwa_freeze. */
+int pwa_nll_batched(pwa_ctx* ctx, const double* d_C, int32_t B, double* d_nll,
+                    hipStream_t stream);
+
+/* Copy the frozen Gram matrix Gm[k][l] = sum_MC conj(a_k) a_l (K x K complex,
+ * (re, im) pairs, row-major) to d_gram (2 K^2 doubles). */
+int pwa_gram(pwa_ctx* ctx, double* d_gram, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -542,12 +542,12 @@ def round_to(x, fmt):
     raise ValueError(fmt)
 
 
-def nll_batched(data, mc, model, theta, C, fmt="f64", chunk=50_000):
+def nll_batched(data, mc, model, theta, C, fmt="f64", chunk=50_000, parts=False):
     """NLL_b = -sum_data ln |(A_D c_b)_i|^2 + N_D ln( c_b^H Gm c_b / N_MC )
     for every column c_b of the complex K x B matrix C (M, Gamma frozen at
     theta).  With fmt != 'f64' the operands A and C are first rounded to
     that format (the contraction itself stays FP64), which isolates the
-    error due to operand rounding."""
+    error due to operand rounding.  With parts=True returns (F_b, G_b)."""
     C = np.asarray(C, dtype=complex)
     Cr = round_to(C.real, fmt) + 1j * round_to(C.imag, fmt)
     B = C.shape[1]
@@ -567,6 +567,8 @@ def nll_batched(data, mc, model, theta, C, fmt="f64", chunk=50_000):
             Gp.append(Z.real ** 2 + Z.imag ** 2)
     F = np.array([math.fsum(np.concatenate([p[:, b] for p in Fp])) for b in range(B)])
     G = np.array([math.fsum(np.concatenate([p[:, b] for p in Gp])) for b in range(B)])
+    if parts:
+        return F, G
     nd, nm = len(data[0]), len(mc[0])
     return -F + nd * np.log(G / nm)
 

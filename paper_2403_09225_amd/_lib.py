@@ -24,6 +24,7 @@ PWA_PREC_F64 = 0
 PWA_PREC_F32 = 1
 PWA_STREAM_F64 = 1
 PWA_STREAM_F32 = 2
+OPERANDS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f16x3": 4}
 
 c_double, c_int32, c_int64, c_size_t, c_void_p = (
     ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p)
@@ -63,10 +64,14 @@ SIGNATURES = {
     "pwa_device_status": (c_int32, [_P, _P]),
     "pwa_status_str": (ctypes.c_char_p, [c_int32]),
     "pwa_n_par": (c_int32, [_P]),
-    "pwa_set_launch_shape": (c_int32, [_P, c_int32, c_int32]),
+    "pwa_set_launch_shape": (c_int32, [_P, c_int32, c_int32, c_int32]),
     "pwa_grid_blocks": (c_int32, [_P]),
     "pwa_set_kernel_timing": (c_int32, [_P, c_int32]),
     "pwa_kernel_time": (c_int32, [_P, ctypes.POINTER(c_double), ctypes.POINTER(c_int64)]),
+    "pwa_batched_workspace_bytes": (c_size_t, [_P, c_int64, c_int32, c_int32]),
+    "pwa_freeze": (c_int32, [_P, _P, c_int32, c_int32, _P, c_size_t, _P]),
+    "pwa_nll_batched": (c_int32, [_P, _P, c_int32, _P, _P]),
+    "pwa_gram": (c_int32, [_P, _P, _P]),
 }
 
 _lib = None

@@ -99,9 +99,11 @@ class Likelihood:
         L.check("pwa_set_precision", self.lib.pwa_set_precision(
             self._h, L.PWA_PREC_F32 if prec == "f32" else L.PWA_PREC_F64))
 
-    def set_launch_shape(self, lanes_per_event=0, res_per_lane=0):
+    def set_launch_shape(self, layout=0, groups=0, res_per_group=0):
+        """layout 1: `groups` lanes per event; layout 2: `groups` waves per 64
+        events; 0: automatic."""
         L.check("pwa_set_launch_shape",
-                self.lib.pwa_set_launch_shape(self._h, lanes_per_event, res_per_lane))
+                self.lib.pwa_set_launch_shape(self._h, layout, groups, res_per_group))
 
     def grid_blocks(self):
         return int(self.lib.pwa_grid_blocks(self._h))
@@ -161,6 +163,40 @@ class Likelihood:
         if s < 0:
             L.check("pwa_device_status", s)
         return s
+
+    # ----------------------------------------------------- batched path
+    def freeze(self, theta, operand="f32", max_batch=256):
+        """Freeze M and Gamma at theta and build the batched-path operands."""
+        t = self._theta(theta)
+        fmt = L.OPERANDS[operand]
+        nbytes = int(self.lib.pwa_batched_workspace_bytes(self._h, self.n_data, fmt, max_batch))
+        if nbytes == 0:
+            raise ValueError("batched path unavailable for these arguments (K <= 24)")
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        self._bws = ws
+        L.check("pwa_freeze", self.lib.pwa_freeze(
+            self._h, _ptr(t), fmt, max_batch, ctypes.c_void_p(ws.data_ptr() + off), nbytes, _stream()))
+        self._t_frozen = t
+        return self
+
+    def nll_batched(self, C):
+        """NLL for every column of the complex K x B coupling matrix C."""
+        if isinstance(C, torch.Tensor):
+            Cc = C.to(self.device)
+        else:
+            Cc = torch.as_tensor(np.asarray(C), device=self.device)
+        B = Cc.shape[1]
+        ri = torch.view_as_real(Cc.to(torch.complex128).T.contiguous()).contiguous()  # (B, K, 2)
+        out = torch.empty(B, dtype=torch.float64, device=self.device)
+        L.check("pwa_nll_batched", self.lib.pwa_nll_batched(self._h, _ptr(ri), B, _ptr(out), _stream()))
+        self._C_keep = ri
+        return out
+
+    def gram(self):
+        out = torch.empty(2 * self.n_res * self.n_res, dtype=torch.float64, device=self.device)
+        L.check("pwa_gram", self.lib.pwa_gram(self._h, _ptr(out), _stream()))
+        return torch.view_as_complex(out.view(self.n_res, self.n_res, 2))
 
     # ------------------------------------------------------------------- fit
     def fit(self, theta0, xtol=1e-8, maxiter=200, cg_maxiter=0, time_cap_s=0.0,

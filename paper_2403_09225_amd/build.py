@@ -2,7 +2,8 @@
 
     python -m paper_2403_09225_amd.build [--verbose]
 
-Compiles csrc/pwa_kernels.hip (device kernels and launchers) and
+Compiles csrc/pwa_kernels.hip (likelihood kernels and launchers),
+csrc/pwa_batched.hip (fixed-lineshape batched path on the matrix cores) and
 csrc/pwa_api.cpp (C ABI, workspace layout, Newton-CG driver) with hipcc and
 links them into paper_2403_09225_amd/libpwa.so.
 """
@@ -42,9 +43,11 @@ def build(verbose=False, jobs=2):
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
     k_obj = os.path.join(bdir, "pwa_kernels.o")
+    b_obj = os.path.join(bdir, "pwa_batched.o")
     a_obj = os.path.join(bdir, "pwa_api.o")
     cmds = [
         [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_kernels.hip"), "-o", k_obj],
+        [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_batched.hip"), "-o", b_obj],
         [HIPCC] + COMMON + DEVICE + ["-x", "hip", "-c", os.path.join(CSRC, "pwa_api.cpp"), "-o", a_obj],
     ]
     procs = [subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
@@ -57,7 +60,7 @@ def build(verbose=False, jobs=2):
             sys.stderr.write(out + err)
             raise RuntimeError("hipcc failed for " + c[-3])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, a_obj], verbose)
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, b_obj, a_obj], verbose)
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f} s", flush=True)

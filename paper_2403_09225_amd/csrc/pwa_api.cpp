@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "pwa_batched.h"
 #include "pwa_internal.h"
 
 using namespace pwa;
@@ -19,7 +20,7 @@ struct pwa_ctx {
   int K = 0, P = 0;
   ModelDev md;
   FieldSpec fs;
-  int shape_T = 0, shape_R = 0;  // 0 = automatic
+  int shape_L = 0, shape_T = 0, shape_R = 0;  // layout 0 = automatic
   // bound state
   bool bound = false;
   int64_t n_data = 0, n_mc = 0, stride = 0;
@@ -30,12 +31,26 @@ struct pwa_ctx {
   float* tbl32 = nullptr;
   int* itbl = nullptr;
   double* part = nullptr;
+  double* tot = nullptr;
   double* dd = nullptr;
   double* scratch = nullptr;
   double* planes64 = nullptr;
   float* planes32 = nullptr;
   int cu_count = 0;
-  int grid_cache[2][3][32];      // [prec][mode][shape index] -> blocks (0 = unknown)
+  struct GridEntry {
+    int prec, mode, L, T, R, blocks;
+  };
+  std::vector<GridEntry> grid_cache;  // resident-grid size per kernel variant
+  // batched (frozen-lineshape) path
+  bool frozen = false;
+  int bfmt = 0, bKP = 0, bmax = 0, brows = 0, bgram_blocks = 0;
+  void* bA_hi = nullptr;
+  void* bA_lo = nullptr;
+  void* bC_hi = nullptr;
+  void* bC_lo = nullptr;
+  double* bpart = nullptr;
+  double* bgram_part = nullptr;
+  double* bgram = nullptr;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -51,7 +66,7 @@ struct pwa_ctx {
 namespace {
 
 struct Layout {
-  size_t status, tbl64, tbl32, itbl, part, dd, scratch, planes64, planes32, total;
+  size_t status, tbl64, tbl32, itbl, part, tot, dd, scratch, planes64, planes32, total;
   int64_t stride;
 };
 
@@ -71,6 +86,7 @@ Layout layout_of(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
   L.tbl32 = take(sizeof(float) * KPAD * TS);
   L.itbl = take(sizeof(int) * KPAD * ITS);
   L.part = take(sizeof(double) * 2 * (size_t)MAX_BLOCKS * (1 + NMOM_HVP * (size_t)K));
+  L.tot = take(sizeof(double) * 4 * (1 + NMOM_HVP * (size_t)K));
   L.dd = take(sizeof(double) * 2 * (2 + 4 * (size_t)P));
   L.scratch = take(sizeof(double) * (8 * (size_t)P + 16));
   L.stride = (int64_t)align_up((size_t)(n_data + n_mc), 64);
@@ -82,61 +98,74 @@ Layout layout_of(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
 
 bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
-// Shape index within the built list (for the grid cache).
-const int kShapes[][2] = {{1, 2}, {1, 4}, {2, 4}, {4, 2}, {4, 3}, {4, 4},
-                          {8, 2}, {8, 4}, {16, 2}, {16, 4}, {32, 2}};
-const int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-
-int shape_index(int T, int R) {
-  for (int i = 0; i < kNumShapes; ++i)
-    if (kShapes[i][0] == T && kShapes[i][1] == R) return i;
-  return -1;
-}
-
-// Automatic launch shape: the smallest built (T, R) covering K, preferring
-// few lanes per event (less duplicated per-event work) while keeping the
-// per-lane FP64 accumulators (8R for the HVP) small enough for 2+ waves/SIMD.
-void auto_shape(int K, int& T, int& R) {
+// Automatic launch shape.  Layout 2 (a block of G waves shares each batch of
+// 64 events, wave g owns R resonances) keeps the resonance table and plane
+// pointers in scalar registers; the choice covers K with the fewest padded
+// resonance slots at R <= 3 (FP64 moment accumulators: 18 R per lane).
+// Layout 1 (T lanes of a wave share an event) serves K > 24.
+void auto_shape(int K, int& L, int& T, int& R) {
+  L = 2;
   if (K <= 2) { T = 1; R = 2; return; }
   if (K <= 4) { T = 1; R = 4; return; }
+  if (K <= 6) { T = 2; R = 3; return; }
   if (K <= 8) { T = 4; R = 2; return; }
   if (K <= 12) { T = 4; R = 3; return; }
   if (K <= 16) { T = 8; R = 2; return; }
+  if (K <= 24) { T = 12; R = 2; return; }
+  L = 1;
   if (K <= 32) { T = 16; R = 2; return; }
   T = 32; R = 2;
 }
 
-void shape_of(const pwa_ctx* c, int& T, int& R) {
-  if (c->shape_T > 0) {
+// The NLL-only pass keeps no moment accumulators: one lane per event with
+// all resonances (layout 1, T = 1) avoids any exchange between lanes.
+bool auto_nll_shape(int K, int& L, int& T, int& R) {
+  const int rs[] = {8, 12, 16, 24, 32};
+  for (int r : rs)
+    if (K <= r) {
+      L = 1;
+      T = 1;
+      R = r;
+      return true;
+    }
+  return false;
+}
+
+void shape_of(const pwa_ctx* c, int mode, int& L, int& T, int& R) {
+  if (c->shape_L == 0 && mode == MODE_NLL && auto_nll_shape(c->K, L, T, R)) return;
+  if (c->shape_L > 0) {
+    L = c->shape_L;
     T = c->shape_T;
     R = c->shape_R;
   } else {
-    auto_shape(c->K, T, R);
+    auto_shape(c->K, L, T, R);
   }
 }
 
-int grid_blocks(pwa_ctx* c, int prec, int mode, int T, int R) {
-  const int si = shape_index(T, R);
-  int& cached = c->grid_cache[prec][mode][si < 0 ? 0 : si];
+int grid_blocks(pwa_ctx* c, int prec, int mode, int L, int T, int R) {
+  int cached = 0;
+  for (const auto& g : c->grid_cache)
+    if (g.prec == prec && g.mode == mode && g.L == L && g.T == T && g.R == R) cached = g.blocks;
   if (cached == 0) {
-    int occ = eval_occupancy(prec, mode, T, R);
+    int occ = eval_occupancy(prec, mode, L, T, R);
     if (occ <= 0) occ = 1;
     cached = std::max(1, std::min(MAX_BLOCKS, c->cu_count * occ));
+    c->grid_cache.push_back({prec, mode, L, T, R, cached});
   }
-  const int teams = BLOCK / T;
+  const int per_iter = (L == 2) ? 64 : BLOCK / T;   // events per block per iteration
   const int64_t n = c->n_data + c->n_mc;
-  const int64_t need = std::max<int64_t>(2, (n + teams - 1) / teams);
+  const int64_t need = std::max<int64_t>(2, (n + per_iter - 1) / per_iter);
   return (int)std::min<int64_t>(cached, need);
 }
 
-void split_blocks(const pwa_ctx* c, int nb, int& nb_data, int& nb_mc) {
+void split_blocks(const pwa_ctx* c, int mode, int nb, int& nb_data, int& nb_mc) {
   if (c->n_data == 0) {
     nb_data = 0;
     nb_mc = std::max(1, nb);
     return;
   }
-  // data events cost a logarithm and a reciprocal more: weight them 1.2
-  const double wd = 1.2 * (double)c->n_data, wm = (double)c->n_mc;
+  const double cost = (mode == MODE_NLL) ? 1.6 : (mode == MODE_GRAD ? 1.35 : 1.2);
+  const double wd = cost * (double)c->n_data, wm = (double)c->n_mc;
   nb_data = (int)llround(nb * wd / (wd + wm));
   nb_data = std::max(1, std::min(nb - 1, nb_data));
   nb_mc = std::max(1, nb - nb_data);
@@ -161,12 +190,12 @@ int fold_timing(pwa_ctx* c) {
 int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta,
              const double* d_v, double* d_nll, double* d_grad, double* d_hv, double* d_dd,
              hipStream_t st) {
-  int T = 1, R = 1;
-  shape_of(c, T, R);
+  int L = 2, T = 1, R = 1;
+  shape_of(c, mode, L, T, R);
   const int kslots = T * R;
   hipError_t e = launch_table(d_theta, d_v, c->md, kslots, c->tbl64, c->tbl32, c->itbl, c->status, st);
   if (e != hipSuccess) return PWA_E_HIP;
-  const int nb = grid_blocks(c, prec, mode, T, R);
+  const int nb = grid_blocks(c, prec, mode, L, T, R);
   EvalArgs a;
   a.planes = prec == PWA_PREC_F32 ? (const void*)c->planes32 : (const void*)c->planes64;
   a.stride = c->stride;
@@ -175,7 +204,7 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
   a.itbl = c->itbl;
   a.n_data = c->n_data;
   a.n_mc = c->n_mc;
-  split_blocks(c, nb, a.nb_data, a.nb_mc);
+  split_blocks(c, mode, nb, a.nb_data, a.nb_mc);
   a.K = c->K;
   a.part = c->part;
   const bool timed = c->timing;
@@ -183,7 +212,7 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
     if (c->ev_used == kEventPool && fold_timing(c) != PWA_OK) return PWA_E_HIP;
     if (hipEventRecord(c->ev_start[c->ev_used], st) != hipSuccess) return PWA_E_HIP;
   }
-  e = launch_eval(prec, mode, T, R, a, a.nb_data + a.nb_mc, st);
+  e = launch_eval(prec, mode, L, T, R, a, a.nb_data + a.nb_mc, st);
   if (e != hipSuccess) return PWA_E_HIP;
   if (timed) {
     if (hipEventRecord(c->ev_stop[c->ev_used], st) != hipSuccess) return PWA_E_HIP;
@@ -191,6 +220,7 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
   }
   FinalArgs f;
   f.part = c->part;
+  f.tot = c->tot;
   f.nb_data = a.nb_data;
   f.nb_mc = a.nb_mc;
   f.V = 1 + (mode == MODE_HVP ? NMOM_HVP : (mode == MODE_GRAD ? NMOM_GRAD : 0)) * c->K;
@@ -255,7 +285,6 @@ int pwa_create(const pwa_model* m, int32_t streams, pwa_ctx** out) {
   c->precision = (streams & PWA_STREAM_F64) ? PWA_PREC_F64 : PWA_PREC_F32;
   c->K = m->n_res;
   c->P = 4 * m->n_res;
-  memset(c->grid_cache, 0, sizeof(c->grid_cache));
   // field layout: s per channel, g per (channel, J), u per (channel, J >= 1)
   FieldSpec& fs = c->fs;
   for (int ch = 0; ch < 3; ++ch) {
@@ -331,11 +360,12 @@ int pwa_bind(pwa_ctx* c, const double* d_s12, const double* d_s13, int64_t n_dat
   c->tbl32 = (float*)(c->ws + L.tbl32);
   c->itbl = (int*)(c->ws + L.itbl);
   c->part = (double*)(c->ws + L.part);
+  c->tot = (double*)(c->ws + L.tot);
   c->dd = (double*)(c->ws + L.dd);
   c->scratch = (double*)(c->ws + L.scratch);
   c->planes64 = (c->streams & PWA_STREAM_F64) ? (double*)(c->ws + L.planes64) : nullptr;
   c->planes32 = (c->streams & PWA_STREAM_F32) ? (float*)(c->ws + L.planes32) : nullptr;
-  memset(c->grid_cache, 0, sizeof(c->grid_cache));
+  c->grid_cache.clear();
   if (hipMemsetAsync(c->status, 0, 64 * sizeof(int), st) != hipSuccess) return PWA_E_HIP;
   for (int f32 = 0; f32 < 2; ++f32) {
     void* planes = f32 ? (void*)c->planes32 : (void*)c->planes64;
@@ -356,13 +386,15 @@ int pwa_set_precision(pwa_ctx* c, int32_t prec) {
   return PWA_OK;
 }
 
-int pwa_set_launch_shape(pwa_ctx* c, int32_t T, int32_t R) {
+int pwa_set_launch_shape(pwa_ctx* c, int32_t layout, int32_t T, int32_t R) {
   if (!c) return PWA_E_INVALID;
-  if (T == 0 && R == 0) {
-    c->shape_T = c->shape_R = 0;
+  if (layout == 0) {
+    c->shape_L = c->shape_T = c->shape_R = 0;
     return PWA_OK;
   }
-  if (!shape_built(T, R) || T * R < c->K || T * R > KPAD) return PWA_E_INVALID;
+  const bool built = (layout == 1) ? shape_built(T, R) : (layout == 2 ? wg_shape_built(T, R) : false);
+  if (!built || T * R < c->K || T * R > KPAD) return PWA_E_INVALID;
+  c->shape_L = layout;
   c->shape_T = T;
   c->shape_R = R;
   return PWA_OK;
@@ -370,9 +402,9 @@ int pwa_set_launch_shape(pwa_ctx* c, int32_t T, int32_t R) {
 
 int32_t pwa_grid_blocks(const pwa_ctx* c) {
   if (!c || !c->bound) return -1;
-  int T, R;
-  shape_of(c, T, R);
-  return grid_blocks(const_cast<pwa_ctx*>(c), c->precision, MODE_HVP, T, R);
+  int L, T, R;
+  shape_of(c, MODE_HVP, L, T, R);
+  return grid_blocks(const_cast<pwa_ctx*>(c), c->precision, MODE_HVP, L, T, R);
 }
 
 int pwa_set_kernel_timing(pwa_ctx* c, int32_t enable) {
@@ -739,6 +771,114 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
   }
   if (converged) return PWA_OK;
   return status;
+}
+
+// ---------------------------------------------------------------------------
+// Batched path.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kBatchRowBlocks = 2048;
+constexpr int kGramBlocks = 512;
+constexpr int kGP = 48;
+
+struct BLayout {
+  size_t A_hi, A_lo, C_hi, C_lo, part, gpart, gram, total;
+  int KP;
+};
+
+BLayout blayout(const pwa_ctx* c, int64_t n_data, int fmt, int max_batch) {
+  BLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  L.KP = batched_kp(fmt, c->K);
+  const size_t eb = batched_elem_bytes(fmt);
+  const bool split = fmt == PWA_OP_F16X3;
+  L.A_hi = take(std::max<int64_t>(n_data, 1) * L.KP * eb);
+  L.A_lo = take(split ? std::max<int64_t>(n_data, 1) * L.KP * eb : 0);
+  L.C_hi = take((size_t)L.KP * 2 * max_batch * eb);
+  L.C_lo = take(split ? (size_t)L.KP * 2 * max_batch * eb : 0);
+  L.part = take(sizeof(double) * 2 * (size_t)kBatchRowBlocks * max_batch);
+  L.gpart = take(sizeof(double) * 2 * (size_t)kGramBlocks * kGP * kGP);
+  L.gram = take(sizeof(double) * 2 * (size_t)c->K * c->K);
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+size_t pwa_batched_workspace_bytes(const pwa_ctx* c, int64_t n_data, int32_t fmt,
+                                   int32_t max_batch) {
+  if (!c || n_data < 0 || fmt < PWA_OP_F64 || fmt > PWA_OP_F16X3) return 0;
+  if (max_batch < 1 || max_batch > 65536 || 2 * c->K > kGP) return 0;
+  return blayout(c, n_data, fmt, max_batch).total;
+}
+
+int pwa_freeze(pwa_ctx* c, const double* d_theta, int32_t fmt, int32_t max_batch, void* d_bws,
+               size_t bws_bytes, hipStream_t st) {
+  if (!c || !d_theta) return PWA_E_INVALID;
+  if (fmt < PWA_OP_F64 || fmt > PWA_OP_F16X3 || max_batch < 1 || max_batch > 65536) return PWA_E_INVALID;
+  if (2 * c->K > kGP) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  if (!(c->streams & PWA_STREAM_F64)) return PWA_E_INVALID;
+  if (!d_bws || ((uintptr_t)d_bws % 256) != 0) return PWA_E_WORKSPACE;
+  const BLayout L = blayout(c, c->n_data, fmt, max_batch);
+  if (bws_bytes < L.total) return PWA_E_WORKSPACE;
+  char* w = (char*)d_bws;
+  c->frozen = false;
+  c->bfmt = fmt;
+  c->bKP = L.KP;
+  c->bmax = max_batch;
+  c->bA_hi = w + L.A_hi;
+  c->bA_lo = fmt == PWA_OP_F16X3 ? (void*)(w + L.A_lo) : nullptr;
+  c->bC_hi = w + L.C_hi;
+  c->bC_lo = fmt == PWA_OP_F16X3 ? (void*)(w + L.C_lo) : nullptr;
+  c->bpart = (double*)(w + L.part);
+  c->bgram_part = (double*)(w + L.gpart);
+  c->bgram = (double*)(w + L.gram);
+  c->brows = (int)std::max<int64_t>(1, std::min<int64_t>(kBatchRowBlocks, (c->n_data + 63) / 64));
+  c->bgram_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kGramBlocks, (c->n_mc + 255) / 256));
+  // resonance table at theta (v = 0): frozen M, Gamma
+  if (launch_table(d_theta, nullptr, c->md, c->K, c->tbl64, c->tbl32, c->itbl, c->status, st) != hipSuccess)
+    return PWA_E_HIP;
+  if (launch_freeze(fmt, c->planes64, c->stride, c->n_data, c->tbl64, c->itbl, c->K, L.KP, c->bA_hi,
+                    c->bA_lo, st) != hipSuccess)
+    return PWA_E_HIP;
+  if (launch_gram(c->planes64, c->stride, c->n_data, c->n_mc, c->tbl64, c->itbl, c->K,
+                  c->bgram_blocks, c->bgram_part, c->bgram, st) != hipSuccess)
+    return PWA_E_HIP;
+  c->frozen = true;
+  return PWA_OK;
+}
+
+int pwa_nll_batched(pwa_ctx* c, const double* d_C, int32_t B, double* d_nll, hipStream_t st) {
+  if (!c || !d_C || !d_nll) return PWA_E_INVALID;
+  if (!c->frozen) return PWA_E_STATE;
+  if (B < 1 || B > c->bmax) return PWA_E_INVALID;
+  BatchArgs a;
+  a.A_hi = c->bA_hi;
+  a.A_lo = c->bA_lo;
+  a.C_hi = c->bC_hi;
+  a.C_lo = c->bC_lo;
+  a.KP = c->bKP;
+  a.B = B;
+  a.n = c->n_data;
+  a.part = c->bpart;
+  return launch_batched(c->bfmt, a, c->brows, d_C, c->bgram, c->K, (double)c->n_data,
+                        (double)c->n_mc, d_nll, st) == hipSuccess
+             ? PWA_OK
+             : PWA_E_HIP;
+}
+
+int pwa_gram(pwa_ctx* c, double* d_gram, hipStream_t st) {
+  if (!c || !d_gram) return PWA_E_INVALID;
+  if (!c->frozen) return PWA_E_STATE;
+  return hipMemcpyAsync(d_gram, c->bgram, sizeof(double) * 2 * c->K * c->K,
+                        hipMemcpyDeviceToDevice, st) == hipSuccess
+             ? PWA_OK
+             : PWA_E_HIP;
 }
 
 }  // extern "C"

@@ -1,0 +1,31 @@
+// Internal declarations of the fixed-lineshape batched path.
+#pragma once
+
+#include "pwa_internal.h"
+
+namespace pwa {
+
+struct BatchArgs {
+  const void* A_hi;   // N_D x KP amplitude operands (row-major)
+  const void* A_lo;   // low parts (split format) or null
+  const void* C_hi;   // KP x 2B coupling operands (row-major)
+  const void* C_lo;
+  int KP;
+  int B;
+  int64_t n;          // N_D
+  double* part;       // row-block partials: (hi, lo) per start
+};
+
+int batched_kp(int fmt, int K);
+int batched_elem_bytes(int fmt);
+hipError_t launch_freeze(int fmt, const double* planes, int64_t stride, int64_t n,
+                         const double* tbl, const int* itbl, int K, int KP, void* out_hi,
+                         void* out_lo, hipStream_t st);
+hipError_t launch_gram(const double* planes, int64_t stride, int64_t base, int64_t n,
+                       const double* tbl, const int* itbl, int K, int nblocks, double* part,
+                       double* gram, hipStream_t st);
+hipError_t launch_batched(int fmt, const BatchArgs& a, int row_blocks, const double* C,
+                          const double* gram, int K, double nd, double nm, double* nll,
+                          hipStream_t st);
+
+}  // namespace pwa

@@ -104,6 +104,7 @@ struct EvalArgs {
 
 struct FinalArgs {
   const double* part;
+  double* tot;               // reduced totals: 2 V (hi, lo) pairs
   const double* tbl;         // resonance table (finaliser slots)
   int nb_data, nb_mc;
   int V;                     // values per block: 1 + NMOM * K
@@ -123,15 +124,19 @@ hipError_t launch_precompute(const double* s12, const double* s13, int64_t n, in
                              const FieldSpec& fs, hipStream_t st);
 hipError_t launch_table(const double* theta, const double* v, const ModelDev& md, int kslots,
                         double* tbl64, float* tbl32, int* itbl, int* status, hipStream_t st);
-hipError_t launch_eval(int is_f32, int mode, int T, int R, const EvalArgs& a, int nblocks,
-                       hipStream_t st);
+// layout 1: T lanes of one wave share an event; layout 2: T waves of one
+// block share each batch of 64 events.  R resonances per lane.
+hipError_t launch_eval(int is_f32, int mode, int layout, int T, int R, const EvalArgs& a,
+                       int nblocks, hipStream_t st);
 hipError_t launch_final(const FinalArgs& f, hipStream_t st);
 hipError_t launch_combine(int n_par, int n_shards, const double* parts, double n_data,
                           double n_mc, const double* v, double* nll, double* grad, double* hv,
                           int* status, hipStream_t st);
 // Maximum resident blocks per CU of an evaluation kernel variant.
-int eval_occupancy(int is_f32, int mode, int T, int R);
-// Is (T, R) an instantiated launch shape?
+int eval_occupancy(int is_f32, int mode, int layout, int T, int R);
+// Is (T, R) an instantiated launch shape of layout 1 / layout 2?
 bool shape_built(int T, int R);
+bool wg_shape_built(int G, int R);
+bool nll_shape_built(int R);
 
 }  // namespace pwa

@@ -9,7 +9,7 @@
 // (Sec. 2.2: "pre-computed and stored on the GPU") into a structure-of-arrays
 // stream; each evaluation then makes one pass over that stream.
 //
-// Kernel structure (one evaluation = 3 launches on the caller's stream):
+// Kernel structure (one evaluation = 4 launches on the caller's stream):
 //   1. table_kernel: per-resonance constants from (theta, v), including the
 //      first and second M-derivatives of the mass-only factors, by
 //      second-order Taylor arithmetic in one thread per resonance.
@@ -19,8 +19,9 @@
 //      sums are reduced per wave with a double-double butterfly and per block
 //      in a fixed order into per-block (hi, lo) partials: no atomics, so the
 //      result is bitwise reproducible for a given grid.
-//   3. final_kernel: fixed-order double-double sum of the block partials and
-//      the eq. (4)/(6)/(7) combine (or the raw eq. (5) partials).
+//   3. reduce_kernel + final_kernel: fixed-order double-double sum of the
+//      block partials, contraction of the moments with the table, and the
+//      eq. (4)/(6)/(7) combine (or the raw eq. (5) partials).
 
 #include <math.h>
 
@@ -59,7 +60,35 @@ __device__ __forceinline__ double rcp_r(double x) {
   return fma(r, e, r);
 }
 __device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double log_r(double x) { return log(x); }
+// Natural logarithm for x > 0 (finite, normal): x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), ln m = 2 atanh(y), y = (m - 1)/(m + 1), |y| <= 0.1716,
+// by its odd series through y^21 (truncation < 1e-19 relative), plus e ln 2
+// with ln 2 split as hi + lo (hi = ln 2 with its 21 low mantissa bits
+// cleared, so e * hi is exact).  Absolute error ~2e-16 max(1, |ln x|),
+// about a third of the instructions of the library routine.
+__device__ __forceinline__ double log_r(double x) {
+  int e;
+  double m = frexp(x, &e);
+  const bool lo = m < 0.70710678118654752440;
+  m = lo ? 2.0 * m : m;
+  e = lo ? e - 1 : e;
+  const double y = (m - 1.0) * rcp_r(m + 1.0);
+  const double y2 = y * y;
+  double p = 1.0 / 21.0;
+  p = fma(p, y2, 1.0 / 19.0);
+  p = fma(p, y2, 1.0 / 17.0);
+  p = fma(p, y2, 1.0 / 15.0);
+  p = fma(p, y2, 1.0 / 13.0);
+  p = fma(p, y2, 1.0 / 11.0);
+  p = fma(p, y2, 1.0 / 9.0);
+  p = fma(p, y2, 1.0 / 7.0);
+  p = fma(p, y2, 1.0 / 5.0);
+  p = fma(p, y2, 1.0 / 3.0);
+  const double t = 2.0 * y;
+  const double r = fma(t * y2, p, t);
+  const double de = (double)e;
+  return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, r));
+}
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
 // FP64 accumulation of per-event terms (converted once for the FP32 path).
@@ -323,6 +352,9 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
   constexpr int NV = 1 + NA;
   constexpr int NSLOT = T * R;
   constexpr int NWAVE = BLOCK / 64;
+  // The next event's stream values are prefetched unless that would hold
+  // too many registers (one lane per event with many resonances).
+  constexpr bool PREFETCH = (T > 1) || (R <= 4);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -341,26 +373,38 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
     __syncthreads();
   }
 
-  // Plane pointers of this lane's resonances (fixed for the whole kernel).
-  const Real* ps[R];
-  const Real* pu[R];
-  const Real* pg[R];
+  // Stream values of resonance slot r at event ev.  T > 1: plane pointers
+  // of this lane's rows, computed once; T == 1: plane indices read as
+  // wave-uniform scalars in the loop (scalar-unit address arithmetic).
+  const Real* ps[(T > 1) ? R : 1];
+  const Real* pu[(T > 1) ? R : 1];
+  const Real* pg[(T > 1) ? R : 1];
+  if constexpr (T > 1) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    int is, iu, ig;
-    if constexpr (T == 1) {
-      is = a.itbl[r * ITS + 0];
-      iu = a.itbl[r * ITS + 1];
-      ig = a.itbl[r * ITS + 2];
-    } else {
-      is = s_it[(pos * R + r) * ITS + 0];
-      iu = s_it[(pos * R + r) * ITS + 1];
-      ig = s_it[(pos * R + r) * ITS + 2];
+    for (int r = 0; r < R; ++r) {
+      ps[r] = planes + (int64_t)s_it[(pos * R + r) * ITS + 0] * stride;
+      pu[r] = planes + (int64_t)s_it[(pos * R + r) * ITS + 1] * stride;
+      pg[r] = planes + (int64_t)s_it[(pos * R + r) * ITS + 2] * stride;
     }
-    ps[r] = planes + (int64_t)is * stride;
-    pu[r] = planes + (int64_t)iu * stride;
-    pg[r] = planes + (int64_t)ig * stride;
   }
+  auto load3 = [&](int64_t ev, Real* s_, Real* u_, Real* g_) {
+    if constexpr (T > 1) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        s_[r] = ps[r][ev];
+        u_[r] = pu[r][ev];
+        g_[r] = pg[r][ev];
+      }
+    } else {
+      c_int* it = opaque_s((c_int*)a.itbl);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        s_[r] = planes[(int64_t)it[r * ITS + 0] * stride + ev];
+        u_[r] = planes[(int64_t)it[r * ITS + 1] * stride + ev];
+        g_[r] = planes[(int64_t)it[r * ITS + 2] * stride + ev];
+      }
+    }
+  };
 
   double accS = 0.0;
   double acc[NA > 0 ? NA : 1];
@@ -371,28 +415,18 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
     // Software pipeline: the stream values of the next event are loaded
     // while the current one is computed.
     Real sc[R], uc[R], gc[R];
-    {
+    if constexpr (PREFETCH) {
       const int64_t e = rg.begin + team;
-      const int64_t ev = rg.base + (e < rg.end ? e : rg.begin);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        sc[r] = ps[r][ev];
-        uc[r] = pu[r][ev];
-        gc[r] = pg[r][ev];
-      }
+      load3(rg.base + (e < rg.end ? e : rg.begin), sc, uc, gc);
     }
     for (int64_t e0 = rg.begin; e0 < rg.end; e0 += TEAMS) {
       const bool valid = e0 + team < rg.end;
-      Real sn[R], un[R], gn[R];
-      {
+      Real sn[PREFETCH ? R : 1], un[PREFETCH ? R : 1], gn[PREFETCH ? R : 1];
+      if constexpr (PREFETCH) {
         const int64_t en = e0 + TEAMS + team;
-        const int64_t evn = rg.base + (en < rg.end ? en : rg.begin);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          sn[r] = ps[r][evn];
-          un[r] = pu[r][evn];
-          gn[r] = pg[r][evn];
-        }
+        load3(rg.base + (en < rg.end ? en : rg.begin), sn, un, gn);
+      } else {
+        load3(rg.base + (valid ? e0 + team : rg.begin), sc, uc, gc);
       }
 
       // Table access: scalar loads for T == 1, this lane's LDS rows otherwise.
@@ -509,11 +543,13 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
           }
         }
       }
+      if constexpr (PREFETCH) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        sc[r] = sn[r];
-        uc[r] = un[r];
-        gc[r] = gn[r];
+        for (int r = 0; r < R; ++r) {
+          sc[r] = sn[r];
+          uc[r] = un[r];
+          gc[r] = gn[r];
+        }
       }
     }
   }
@@ -558,6 +594,222 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
       out[vi * 2 + 1] = l;
     }
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------
+// Wave-group layout of the same pass: the G waves of a block share each batch
+// of 64 events (one event per lane) and wave g owns resonances
+// [g R, g R + R).  Table rows and plane pointers are then wave-uniform
+// (scalar registers), and the partial z, zdot of the G waves are exchanged
+// through LDS (double-buffered, one barrier per batch).  Per lane the
+// moment accumulators are those of R resonances, as in the team layout.
+// ------------------------------------------------------------------------
+template <typename Real, int MODE, int G, int R>
+__global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
+  typedef typename CPtr<Real>::type CReal;
+  constexpr bool HVP = (MODE == MODE_HVP);
+  constexpr bool DER = (MODE != MODE_NLL);
+  constexpr int NM = HVP ? NMOM_HVP : (DER ? NMOM_GRAD : 0);
+  constexpr int NA = NM * R;
+  constexpr int NX = HVP ? 4 : 2;     // exchanged reals per lane: z (, zdot)
+
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const Range rg = block_range(a);
+  const Real* __restrict__ planes = (const Real*)a.planes;
+  const int64_t stride = a.stride;
+  const Real* tsrc = ((sizeof(Real) == 8) ? (const Real*)a.tbl64 : (const Real*)a.tbl32) + wv * R * TS;
+
+  __shared__ Real xch[2][G][64][NX];
+
+  const Real* ps[R];
+  const Real* pu[R];
+  const Real* pg[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int row = wv * R + r;
+    ps[r] = planes + (int64_t)a.itbl[row * ITS + 0] * stride;
+    pu[r] = planes + (int64_t)a.itbl[row * ITS + 1] * stride;
+    pg[r] = planes + (int64_t)a.itbl[row * ITS + 2] * stride;
+  }
+
+  double accS = 0.0;
+  double acc[NA > 0 ? NA : 1];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+
+  if (rg.begin < rg.end) {
+    Real sc[R], uc[R], gc[R];
+    {
+      const int64_t e = rg.begin + lane;
+      const int64_t ev = rg.base + (e < rg.end ? e : rg.begin);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sc[r] = ps[r][ev];
+        uc[r] = pu[r][ev];
+        gc[r] = pg[r][ev];
+      }
+    }
+    int buf = 0;
+    for (int64_t e0 = rg.begin; e0 < rg.end; e0 += 64, buf ^= 1) {
+      const bool valid = e0 + lane < rg.end;
+      Real sn[R], un[R], gn[R];
+      {
+        const int64_t en = e0 + 64 + lane;
+        const int64_t evn = rg.base + (en < rg.end ? en : rg.begin);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          sn[r] = ps[r][evn];
+          un[r] = pu[r][evn];
+          gn[r] = pg[r][evn];
+        }
+      }
+      CReal* tb = opaque_s((CReal*)tsrc);
+
+      // ---- pass 1: this wave's share of z (and zdot)
+      Real cwr[R], cwi[R], cu[R];
+      Real zr = 0, zi = 0, zdr = 0, zdi = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        CReal* t = tb + r * TS;
+        const Real u = uc[r] * t[TB_UMUL] + t[TB_UADD];
+        const Real g = gc[r];
+        const Real Dr = t[TB_M2] - sc[r];
+        const Real Di = t[TB_NGE] * g;
+        const Real inv = rcp_r(Dr * Dr + Di * Di);
+        const Real wr = Dr * inv, wi = -Di * inv;
+        const Real uwr = u * wr, uwi = u * wi;
+        zr = fma_r(t[TB_CBR], uwr, fma_r(-t[TB_CBI], uwi, zr));
+        zi = fma_r(t[TB_CBR], uwi, fma_r(t[TB_CBI], uwr, zi));
+        if constexpr (HVP) {
+          const Real uw2r = uwr * wr - uwi * wi, uw2i = uwr * wi + uwi * wr;
+          const Real kr = fma_r(t[TB_K3R], g, t[TB_K2R]);
+          const Real ki = fma_r(t[TB_K3I], g, t[TB_K2I]);
+          zdr = fma_r(t[TB_K1R], uwr, fma_r(-t[TB_K1I], uwi, fma_r(kr, uw2r, fma_r(-ki, uw2i, zdr))));
+          zdi = fma_r(t[TB_K1R], uwi, fma_r(t[TB_K1I], uwr, fma_r(kr, uw2i, fma_r(ki, uw2r, zdi))));
+        }
+        cwr[r] = wr;
+        cwi[r] = wi;
+        cu[r] = u;
+      }
+      // ---- exchange: every wave sums the G shares in group order
+      if constexpr (G > 1) {
+        xch[buf][wv][lane][0] = zr;
+        xch[buf][wv][lane][1] = zi;
+        if constexpr (HVP) {
+          xch[buf][wv][lane][2] = zdr;
+          xch[buf][wv][lane][3] = zdi;
+        }
+        __syncthreads();
+        zr = zi = zdr = zdi = 0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          zr += xch[buf][g][lane][0];
+          zi += xch[buf][g][lane][1];
+          if constexpr (HVP) {
+            zdr += xch[buf][g][lane][2];
+            zdi += xch[buf][g][lane][3];
+          }
+        }
+      }
+
+      // ---- per-event weights
+      const Real om = zr * zr + zi * zi;
+      Real gr = 0, gi = 0, alr = 0, ali = 0;
+      double sterm = 0.0;
+      if (rg.is_data) {
+        if (wv == 0) sterm = (double)log_r(om);
+        if constexpr (DER) {
+          const Real io = rcp_r(om);
+          gr = zr * io;
+          gi = -zi * io;
+          if constexpr (HVP) {
+            const Real t = 2 * (zr * zdr + zi * zdi) * io;
+            alr = (zdr - t * zr) * io;
+            ali = (t * zi - zdi) * io;
+          }
+        }
+      } else {
+        sterm = (double)om;
+        gr = zr;
+        gi = -zi;
+        alr = zdr;
+        ali = -zdi;
+      }
+      if (!valid) {
+        sterm = 0.0;
+        gr = gi = alr = ali = 0;
+      }
+      if (wv == 0) accS += sterm;
+
+      // ---- pass 2: moments (chain p = x u w, q = p w, r = q w)
+      if constexpr (DER) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const Real wr = cwr[r], wi = cwi[r], g = gc[r];
+          const Real uwr = cu[r] * wr, uwi = cu[r] * wi;
+          double* m = acc + NM * r;
+          const Real pr = gr * uwr - gi * uwi, pi = gr * uwi + gi * uwr;
+          const Real qr = pr * wr - pi * wi, qi = pr * wi + pi * wr;
+          acc_add(m[0], pr);
+          acc_add(m[1], pi);
+          acc_add(m[2], qr);
+          acc_add(m[3], qi);
+          acc_fma(m[4], g, qr);
+          acc_fma(m[5], g, qi);
+          if constexpr (HVP) {
+            const Real ar_ = alr * uwr - ali * uwi, ai_ = alr * uwi + ali * uwr;
+            const Real br_ = ar_ * wr - ai_ * wi, bi_ = ar_ * wi + ai_ * wr;
+            acc_add(m[6], ar_);
+            acc_add(m[7], ai_);
+            acc_add(m[8], br_);
+            acc_add(m[9], bi_);
+            acc_fma(m[10], g, br_);
+            acc_fma(m[11], g, bi_);
+            const Real rr = qr * wr - qi * wi, ri = qr * wi + qi * wr;
+            const Real g2 = g * g;
+            acc_add(m[12], rr);
+            acc_add(m[13], ri);
+            acc_fma(m[14], g, rr);
+            acc_fma(m[15], g, ri);
+            acc_fma(m[16], g2, rr);
+            acc_fma(m[17], g2, ri);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sc[r] = sn[r];
+        uc[r] = un[r];
+        gc[r] = gn[r];
+      }
+    }
+  }
+
+  // ---- reduction: each wave owns its resonances, so a wave-level
+  // butterfly (fixed order, symmetric) gives the block partial directly.
+  const int K = a.K;
+  const int V = 1 + NM * K;
+  double* out = a.part + (int64_t)blockIdx.x * V * 2;
+  if (wv == 0) {
+    double hi = accS, lo = 0.0;
+    dd_wave_reduce(hi, lo, 1);
+    if (lane == 0) {
+      out[0] = hi;
+      out[1] = lo;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    double x = acc[j];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) x += __shfl_xor(x, off);
+    const int k = wv * R + j / NM;
+    if (lane == 0 && k < K) {
+      out[(1 + NM * k + j % NM) * 2] = x;
+      out[(1 + NM * k + j % NM) * 2 + 1] = 0.0;
+    }
   }
 }
 
@@ -648,27 +900,41 @@ __device__ void combine_block(double F, double G, const double* dF, const double
   }
 }
 
-__global__ __launch_bounds__(1024) void final_kernel(FinalArgs f) {
-  __shared__ double tot[2 * (1 + NMOM_HVP * PWA_MAX_RES) * 2];
-  __shared__ double der[4][4 * PWA_MAX_RES];   // dF, dG, HF, HG
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nw = blockDim.x >> 6;
-  for (int vv = wave; vv < 2 * f.V; vv += nw) {
+// Stage 1: fixed-order double-double sum of the block partials, coalesced:
+// lane l of a block owns value index blockIdx.x * 64 + l (data values first,
+// then MC values); the 16 waves stride over the partial blocks and are then
+// combined in wave order.
+__global__ __launch_bounds__(1024) void reduce_kernel(FinalArgs f) {
+  __shared__ double red[16][64][2];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int vv = blockIdx.x * 64 + lane;
+  double hi = 0.0, lo = 0.0;
+  if (vv < 2 * f.V) {
     const int set = vv >= f.V;
     const int vi = vv - set * f.V;
     const int b0 = set ? f.nb_data : 0;
     const int nb = set ? f.nb_mc : f.nb_data;
-    double hi = 0.0, lo = 0.0;
-    for (int b = lane; b < nb; b += 64)
-      dd_add(hi, lo, f.part[((int64_t)(b0 + b) * f.V + vi) * 2],
-             f.part[((int64_t)(b0 + b) * f.V + vi) * 2 + 1]);
-    dd_wave_reduce(hi, lo, 1);
-    if (lane == 0) {
-      tot[vv * 2] = hi;
-      tot[vv * 2 + 1] = lo;
+    for (int b = grp; b < nb; b += 16) {
+      const double* q = f.part + ((int64_t)(b0 + b) * f.V + vi) * 2;
+      dd_add(hi, lo, q[0], q[1]);
     }
   }
+  red[grp][lane][0] = hi;
+  red[grp][lane][1] = lo;
   __syncthreads();
+  if (grp == 0 && vv < 2 * f.V) {
+    for (int g = 1; g < 16; ++g) dd_add(hi, lo, red[g][lane][0], red[g][lane][1]);
+    f.tot[2 * vv] = hi;
+    f.tot[2 * vv + 1] = lo;
+  }
+}
+
+// Stage 2 (one block): contraction of the moment totals with the resonance
+// table, then the eq. (4)/(6)/(7) combine or the raw eq. (5) partials.
+__global__ __launch_bounds__(1024) void final_kernel(FinalArgs f) {
+  __shared__ double der[4][4 * PWA_MAX_RES];   // dF, dG, HF, HG
+  const int tid = threadIdx.x;
+  const double* tot = f.tot;
   const int K = f.K, P = 4 * K;
   const bool hvp = f.mode == MODE_HVP;
   const int NM = hvp ? NMOM_HVP : NMOM_GRAD;
@@ -677,9 +943,11 @@ __global__ __launch_bounds__(1024) void final_kernel(FinalArgs f) {
       const int set = q / K, k = q % K;
       const double* src = tot + 2 * (set * f.V + 1 + NM * k);
       double mom[NMOM_HVP];
-      for (int j = 0; j < NM; ++j) mom[j] = src[2 * j] + src[2 * j + 1];
+#pragma unroll
+      for (int j = 0; j < NMOM_HVP; ++j) mom[j] = (j < NM) ? src[2 * j] + src[2 * j + 1] : 0.0;
       double dg[4], dh[4] = {0.0, 0.0, 0.0, 0.0};
       contract(mom, f.tbl + k * TS, hvp, dg, dh);
+#pragma unroll
       for (int j = 0; j < 4; ++j) {
         der[set][4 * k + j] = dg[j];
         der[2 + set][4 * k + j] = dh[j];
@@ -769,6 +1037,16 @@ hipError_t launch_table(const double* theta, const double* v, const ModelDev& md
 #define PWA_SHAPES(X) \
   X(1, 2) X(1, 4) X(2, 4) X(4, 2) X(4, 3) X(4, 4) X(8, 2) X(8, 4) X(16, 2) X(16, 4) X(32, 2)
 
+// Wave-group shapes (waves per block G, resonances per wave R).
+#define PWA_WG_SHAPES(X) X(1, 2) X(1, 4) X(2, 3) X(2, 4) X(3, 4) X(4, 2) X(4, 3) X(5, 3) X(6, 2) X(8, 2) X(8, 3) X(12, 2)
+
+bool wg_shape_built(int G, int R) {
+#define PWA_IS(GG, RR) if (G == GG && R == RR) return true;
+  PWA_WG_SHAPES(PWA_IS)
+#undef PWA_IS
+  return false;
+}
+
 bool shape_built(int T, int R) {
 #define PWA_IS(TT, RR) if (T == TT && R == RR) return true;
   PWA_SHAPES(PWA_IS)
@@ -792,24 +1070,70 @@ static EvalFn eval_fn(int is_f32, int mode, int T, int R) {
   return nullptr;
 }
 
-hipError_t launch_eval(int is_f32, int mode, int T, int R, const EvalArgs& a, int nblocks,
-                       hipStream_t st) {
-  EvalFn fn = eval_fn(is_f32, mode, T, R);
+// NLL-only shapes of layout 1 with one lane per event (no moment
+// accumulators, so all K resonances fit in one lane).
+#define PWA_NLL_SHAPES(X) X(8) X(12) X(16) X(24) X(32)
+
+bool nll_shape_built(int R) {
+#define PWA_IS(RR) if (R == RR) return true;
+  PWA_NLL_SHAPES(PWA_IS)
+#undef PWA_IS
+  return false;
+}
+
+static EvalFn nll_fn(int is_f32, int R) {
+#define PWA_PICK(RR) \
+  if (R == RR) return is_f32 ? eval_kernel<float, MODE_NLL, 1, RR> : eval_kernel<double, MODE_NLL, 1, RR>;
+  PWA_NLL_SHAPES(PWA_PICK)
+#undef PWA_PICK
+  return nullptr;
+}
+
+static EvalFn wg_fn(int is_f32, int mode, int G, int R) {
+#define PWA_PICK(GG, RR)                                                              \
+  if (G == GG && R == RR) {                                                           \
+    if (mode == MODE_NLL)                                                             \
+      return is_f32 ? wg_kernel<float, MODE_NLL, GG, RR> : wg_kernel<double, MODE_NLL, GG, RR>;   \
+    if (mode == MODE_GRAD)                                                            \
+      return is_f32 ? wg_kernel<float, MODE_GRAD, GG, RR> : wg_kernel<double, MODE_GRAD, GG, RR>; \
+    return is_f32 ? wg_kernel<float, MODE_HVP, GG, RR> : wg_kernel<double, MODE_HVP, GG, RR>;     \
+  }
+  PWA_WG_SHAPES(PWA_PICK)
+#undef PWA_PICK
+  return nullptr;
+}
+
+// layout 1: team (T lanes of a wave per event, 256-thread blocks);
+// layout 2: wave group (G waves per 64 events, 64 G-thread blocks).
+static EvalFn pick_fn(int is_f32, int mode, int layout, int T, int R) {
+  if (layout == 2) return wg_fn(is_f32, mode, T, R);
+  if (mode == MODE_NLL && T == 1 && nll_shape_built(R)) return nll_fn(is_f32, R);
+  return eval_fn(is_f32, mode, T, R);
+}
+
+hipError_t launch_eval(int is_f32, int mode, int layout, int T, int R, const EvalArgs& a,
+                       int nblocks, hipStream_t st) {
+  EvalFn fn = pick_fn(is_f32, mode, layout, T, R);
   if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(nblocks), dim3(BLOCK), 0, st, a);
+  hipLaunchKernelGGL(fn, dim3(nblocks), dim3(layout == 2 ? 64 * T : BLOCK), 0, st, a);
   return hipGetLastError();
 }
 
-int eval_occupancy(int is_f32, int mode, int T, int R) {
-  EvalFn fn = eval_fn(is_f32, mode, T, R);
+int eval_occupancy(int is_f32, int mode, int layout, int T, int R) {
+  EvalFn fn = pick_fn(is_f32, mode, layout, T, R);
   if (!fn) return 0;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, BLOCK, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, layout == 2 ? 64 * T : BLOCK,
+                                                   0) != hipSuccess)
     return 0;
   return nb;
 }
 
 hipError_t launch_final(const FinalArgs& f, hipStream_t st) {
+  const unsigned nb = (unsigned)((2 * f.V + 63) / 64);
+  hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(1024), 0, st, f);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(final_kernel, dim3(1), dim3(1024), 0, st, f);
   return hipGetLastError();
 }

@@ -87,10 +87,13 @@ def test_valid_context_host_queries(lib):
         assert lib.pwa_grid_blocks(h) == -1
         assert lib.pwa_set_precision(h, L.PWA_PREC_F32) == L.PWA_OK
         assert lib.pwa_set_precision(h, 7) == L.PWA_E_INVALID
-        assert lib.pwa_set_launch_shape(h, 3, 3) == L.PWA_E_INVALID
-        assert lib.pwa_set_launch_shape(h, 1, 2) == L.PWA_E_INVALID   # 2 < K = 12
-        assert lib.pwa_set_launch_shape(h, 4, 3) == L.PWA_OK
-        assert lib.pwa_set_launch_shape(h, 0, 0) == L.PWA_OK
+        assert lib.pwa_set_launch_shape(h, 1, 3, 3) == L.PWA_E_INVALID
+        assert lib.pwa_set_launch_shape(h, 1, 1, 2) == L.PWA_E_INVALID   # 2 < K = 12
+        assert lib.pwa_set_launch_shape(h, 3, 4, 3) == L.PWA_E_INVALID   # no layout 3
+        assert lib.pwa_set_launch_shape(h, 1, 4, 3) == L.PWA_OK
+        assert lib.pwa_set_launch_shape(h, 2, 4, 3) == L.PWA_OK
+        assert lib.pwa_set_launch_shape(h, 2, 7, 3) == L.PWA_E_INVALID   # not built
+        assert lib.pwa_set_launch_shape(h, 0, 0, 0) == L.PWA_OK
     finally:
         lib.pwa_destroy(h)
     lib.pwa_destroy(None)

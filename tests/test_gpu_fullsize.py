@@ -89,10 +89,14 @@ def test_fullsize_central_differences(cfg1):
     fd = (fp - fm) / (2 * h)
     gd = float(_np(g) @ d)
     assert abs(fd - gd) <= 1e-5 * np.abs(_np(g)).max() * np.abs(d).sum()
-    gp = _np(lik.grad(th + h * d)[1])
-    gm = _np(lik.grad(th - h * d)[1])
-    hfd = (gp - gm) / (2 * h)
-    assert np.max(np.abs(hfd - _np(hv))) <= 1e-4 * np.max(np.abs(_np(hv)))
+    # Richardson-extrapolated central difference of the gradient, error
+    # O(h^4): at this size events close to narrow poles make the plain
+    # central difference's O(h^2) term reach ~5e-4 relative at h = 1e-6
+    # (the oracle shows the same on subsamples).
+    def cd(hh):
+        return (_np(lik.grad(th + hh * d)[1]) - _np(lik.grad(th - hh * d)[1])) / (2 * hh)
+    hfd = (4.0 * cd(h / 2) - cd(h)) / 3.0
+    assert np.max(np.abs(hfd - _np(hv))) <= 1e-5 * np.max(np.abs(_np(hv)))
 
 
 def test_fullsize_shards_and_determinism(cfg1):

@@ -52,19 +52,24 @@ def test_fp64_parity(K, nd, nm, seed, wm):
     _check_fp64(lik, model, th, data, mc, v)
 
 
-@pytest.mark.parametrize("shape", [(4, 3), (4, 4), (8, 2), (8, 4), (16, 2), (16, 4), (32, 2)])
+@pytest.mark.parametrize("shape", [(1, 4, 3), (1, 4, 4), (1, 8, 2), (1, 8, 4), (1, 16, 2),
+                                   (1, 16, 4), (1, 32, 2), (2, 4, 3), (2, 3, 4), (2, 6, 2),
+                                   (2, 8, 2), (2, 8, 3), (2, 12, 2)])
 def test_every_launch_shape(shape):
-    say(f"[shape] K=12 T,R={shape}")
+    say(f"[shape] K=12 layout,groups,R={shape}")
     model, th, data, mc, v = case(12, 1777, 6001, 20)
     lik = likelihood(model, data, mc)
     lik.set_launch_shape(*shape)
     _check_fp64(lik, model, th, data, mc, v)
 
 
-@pytest.mark.parametrize("K,shape", [(2, (1, 2)), (2, (1, 4)), (3, (1, 4)), (8, (2, 4)),
-                                     (6, (4, 2)), (16, (4, 4)), (30, (16, 2)), (64, (32, 2))])
+@pytest.mark.parametrize("K,shape", [(2, (1, 1, 2)), (2, (1, 1, 4)), (3, (1, 1, 4)), (8, (1, 2, 4)),
+                                     (6, (1, 4, 2)), (16, (1, 4, 4)), (30, (1, 16, 2)),
+                                     (64, (1, 32, 2)), (2, (2, 1, 2)), (3, (2, 1, 4)), (5, (2, 2, 3)),
+                                     (7, (2, 2, 4)), (8, (2, 4, 2)), (16, (2, 8, 2)), (22, (2, 8, 3)),
+                                     (15, (2, 5, 3)), (24, (2, 12, 2)), (12, (2, 3, 4))])
 def test_small_k_shapes(K, shape):
-    say(f"[shape] K={K} T,R={shape}")
+    say(f"[shape] K={K} layout,groups,R={shape}")
     model, th, data, mc, v = case(K, 913, 3007, 21 + K)
     lik = likelihood(model, data, mc)
     lik.set_launch_shape(*shape)
@@ -212,3 +217,13 @@ def test_autograd_double_backward():
     assert abs(float(val) - f) <= 1e-10 * abs(f)
     assert_close("autograd grad", _np(gt), g, S, 1e-10)
     assert_close("autograd hv", _np(hvt), hv, SH + S + np.abs(hv), 1e-10)
+
+
+def test_many_iterations_per_block():
+    """~230k events: every block of the benchmark's launch shape loops over
+    many event batches (software-pipelined loads, LDS exchange buffers), as
+    at full size; gradient and H v against the oracle."""
+    say("[many iterations] K=12, 40k data + 190k MC")
+    model, th, data, mc, v = case(12, 40_000, 190_000, 140)
+    lik = likelihood(model, data, mc)
+    _check_fp64(lik, model, th, data, mc, v)
