@@ -146,6 +146,17 @@ int pwa_grad(pwa_ctx* ctx, const double* d_theta, double* d_nll, double* d_grad,
 int pwa_hvp(pwa_ctx* ctx, const double* d_theta, const double* d_v, double* d_hv,
             double* d_nll, double* d_grad, hipStream_t stream);
 
+/* Per-event intensity omega(x) = |sum_k c_k a_k(x)|^2 of eq. (1) at theta
+ * for the bound data events (which = 0; n_data outputs) or MC events
+ * (which = 1; n_mc outputs), in the event order given to pwa_bind, using the
+ * event stream of the current precision and FP64 arithmetic.  d_out: device,
+ * caller-owned, one double per event.  Used to draw events from the model by
+ * accept-reject (toy data).  A mass at or below its threshold sets the device
+ * status (pwa_device_status) and leaves the outputs unspecified.
+ * Errors: PWA_E_INVALID, PWA_E_STATE (unbound), PWA_E_HIP. */
+int pwa_intensity(pwa_ctx* ctx, const double* d_theta, int32_t which, double* d_out,
+                  hipStream_t stream);
+
 /* Un-combined per-shard sums of eq. (5) and their derivatives for the bound
  * events (one GPU's share in the paper's multi-GPU scheme, Sec. 2.3).
  * d_part receives 2*(2+4P) doubles: (hi, lo) double-double pairs of
@@ -243,13 +254,22 @@ int pwa_kernel_time(pwa_ctx* ctx, double* total_ms, int64_t* n_launches);
  * normalisation is G_b = c_b^H Gm c_b with the K x K Gram matrix
  * Gm = sum_MC conj(a_k) a_l.  NLL_b = -F_b + N_D ln(G_b / N_MC) (eq. (3)).
  * ------------------------------------------------------------------------- */
+/* Operand formats.  A rounding of a coupling shifts every event's log the
+ * same way (the NLL error grows like N_D times the gradient in c), while a
+ * rounding of an amplitude is independent from event to event (its error
+ * grows like sqrt(N_D)); the accurate formats therefore represent the
+ * couplings as a sum of parts.  BF16 and FP16 round both operands once and
+ * are the fast, low-precision formats. */
 typedef enum pwa_operand {
   PWA_OP_F64 = 0,   /* FP64 operands, FP64 matrix-core accumulation          */
-  PWA_OP_F32 = 1,   /* FP32 operands, FP32 accumulation                      */
+  PWA_OP_F32 = 1,   /* FP32 amplitudes; couplings as FP32 hi + lo (two
+                       products); FP32 accumulation                          */
   PWA_OP_BF16 = 2,  /* BF16 operands, FP32 accumulation                      */
   PWA_OP_F16 = 3,   /* FP16 operands, FP32 accumulation                      */
-  PWA_OP_F16X3 = 4  /* FP16 hi + lo split of both operands, three products
-                       (hi*hi + hi*lo + lo*hi), FP32 accumulation            */
+  PWA_OP_F16X3 = 4  /* FP16 amplitudes as hi + lo; couplings, scaled per
+                       start by a power of two, as three FP16 parts; four
+                       products (hi*c0 + hi*c1 + hi*c2 + lo*c0), FP32
+                       accumulation                                          */
 } pwa_operand;
 
 /* Device workspace (bytes) of the batched path for n_data data events,

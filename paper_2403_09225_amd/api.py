@@ -147,6 +147,15 @@ class Likelihood:
             ctypes.c_void_p(base), ctypes.c_void_p(base + 8), _stream()))
         return out[1 + self.n_par:], out[0], out[1:1 + self.n_par]
 
+    def intensity(self, theta, which="data"):
+        """Per-event omega(x) at theta for the bound data or MC events (eq. (1))."""
+        t = self._theta(theta)
+        w = {"data": 0, "mc": 1}[which]
+        n = self.n_data if w == 0 else self.n_mc
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        L.check("pwa_intensity", self.lib.pwa_intensity(self._h, _ptr(t), w, _ptr(out), _stream()))
+        return out
+
     def partials(self, theta, v=None):
         """(hi, lo) pairs of [F, G, dF, dG, H_F v, H_G v] (eq. (5) and derivatives)."""
         t = self._theta(theta)

@@ -48,7 +48,9 @@ struct pwa_ctx {
   void* bA_lo = nullptr;
   void* bC_hi = nullptr;
   void* bC_lo = nullptr;
+  void* bC_lo2 = nullptr;
   double* bpart = nullptr;
+  double* bpart2 = nullptr;
   double* bgram_part = nullptr;
   double* bgram = nullptr;
   // kernel timing
@@ -453,6 +455,22 @@ int pwa_hvp(pwa_ctx* c, const double* d_theta, const double* d_v, double* d_hv, 
                   nullptr, st);
 }
 
+int pwa_intensity(pwa_ctx* c, const double* d_theta, int32_t which, double* d_out,
+                  hipStream_t st) {
+  if (!c || !d_theta || !d_out || (which != 0 && which != 1)) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  const int64_t n = which ? c->n_mc : c->n_data;
+  const int64_t base = which ? c->n_data : 0;
+  if (launch_table(d_theta, nullptr, c->md, c->K, c->tbl64, c->tbl32, c->itbl, c->status, st) !=
+      hipSuccess)
+    return PWA_E_HIP;
+  const bool f32 = c->precision == PWA_PREC_F32;
+  return launch_intensity(f32, f32 ? (const void*)c->planes32 : (const void*)c->planes64, c->stride,
+                          base, n, c->tbl64, c->itbl, c->K, d_out, st) == hipSuccess
+             ? PWA_OK
+             : PWA_E_HIP;
+}
+
 int pwa_partials(pwa_ctx* c, const double* d_theta, const double* d_v, double* d_part,
                  hipStream_t st) {
   if (!c || !d_theta || !d_part) return PWA_E_INVALID;
@@ -782,7 +800,7 @@ constexpr int kGramBlocks = 512;
 constexpr int kGP = 48;
 
 struct BLayout {
-  size_t A_hi, A_lo, C_hi, C_lo, part, gpart, gram, total;
+  size_t A_hi, A_lo, C_hi, C_lo, C_lo2, part, part2, gpart, gram, total;
   int KP;
 };
 
@@ -799,9 +817,12 @@ BLayout blayout(const pwa_ctx* c, int64_t n_data, int fmt, int max_batch) {
   const bool split = fmt == PWA_OP_F16X3;
   L.A_hi = take(std::max<int64_t>(n_data, 1) * L.KP * eb);
   L.A_lo = take(split ? std::max<int64_t>(n_data, 1) * L.KP * eb : 0);
+  const int ncp = fmt == PWA_OP_F32 ? 2 : (split ? 3 : 1);   // coupling parts
   L.C_hi = take((size_t)L.KP * 2 * max_batch * eb);
-  L.C_lo = take(split ? (size_t)L.KP * 2 * max_batch * eb : 0);
+  L.C_lo = take(ncp > 1 ? (size_t)L.KP * 2 * max_batch * eb : 0);
+  L.C_lo2 = take(ncp > 2 ? (size_t)L.KP * 2 * max_batch * eb : 0);
   L.part = take(sizeof(double) * 2 * (size_t)kBatchRowBlocks * max_batch);
+  L.part2 = take(sizeof(double) * 2 * (size_t)kBatchChunks * max_batch);
   L.gpart = take(sizeof(double) * 2 * (size_t)kGramBlocks * kGP * kGP);
   L.gram = take(sizeof(double) * 2 * (size_t)c->K * c->K);
   L.total = off;
@@ -834,8 +855,10 @@ int pwa_freeze(pwa_ctx* c, const double* d_theta, int32_t fmt, int32_t max_batch
   c->bA_hi = w + L.A_hi;
   c->bA_lo = fmt == PWA_OP_F16X3 ? (void*)(w + L.A_lo) : nullptr;
   c->bC_hi = w + L.C_hi;
-  c->bC_lo = fmt == PWA_OP_F16X3 ? (void*)(w + L.C_lo) : nullptr;
+  c->bC_lo = (fmt == PWA_OP_F16X3 || fmt == PWA_OP_F32) ? (void*)(w + L.C_lo) : nullptr;
+  c->bC_lo2 = fmt == PWA_OP_F16X3 ? (void*)(w + L.C_lo2) : nullptr;
   c->bpart = (double*)(w + L.part);
+  c->bpart2 = (double*)(w + L.part2);
   c->bgram_part = (double*)(w + L.gpart);
   c->bgram = (double*)(w + L.gram);
   c->brows = (int)std::max<int64_t>(1, std::min<int64_t>(kBatchRowBlocks, (c->n_data + 63) / 64));
@@ -862,10 +885,12 @@ int pwa_nll_batched(pwa_ctx* c, const double* d_C, int32_t B, double* d_nll, hip
   a.A_lo = c->bA_lo;
   a.C_hi = c->bC_hi;
   a.C_lo = c->bC_lo;
+  a.C_lo2 = c->bC_lo2;
   a.KP = c->bKP;
   a.B = B;
   a.n = c->n_data;
   a.part = c->bpart;
+  a.part2 = c->bpart2;
   return launch_batched(c->bfmt, a, c->brows, d_C, c->bgram, c->K, (double)c->n_data,
                         (double)c->n_mc, d_nll, st) == hipSuccess
              ? PWA_OK

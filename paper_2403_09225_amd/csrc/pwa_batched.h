@@ -9,12 +9,16 @@ struct BatchArgs {
   const void* A_hi;   // N_D x KP amplitude operands (row-major)
   const void* A_lo;   // low parts (split format) or null
   const void* C_hi;   // KP x 2B coupling operands (row-major)
-  const void* C_lo;
+  const void* C_lo;   // second coupling part (FP32 and split formats) or null
+  const void* C_lo2;  // third coupling part (split format) or null
   int KP;
   int B;
   int64_t n;          // N_D
   double* part;       // row-block partials: (hi, lo) per start
+  double* part2;      // chunk partials of the row-block partials: (hi, lo) per start
 };
+
+constexpr int kBatchChunks = 32;   // chunks of the first stage of the per-start sum
 
 int batched_kp(int fmt, int K);
 int batched_elem_bytes(int fmt);

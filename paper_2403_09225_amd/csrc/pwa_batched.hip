@@ -128,11 +128,29 @@ __global__ __launch_bounds__(256) void freeze_kernel(const double* __restrict__ 
   }
 }
 
+// Power-of-two column scale of the split FP16 format: start b's couplings are
+// multiplied by 2^shift so that their largest real component lies in
+// [2^10, 2^11); the three FP16 parts of every component then stay in the
+// normal FP16 range.  Z scales by 2^shift and ln |Z|^2 by 2 shift ln 2, which
+// the final kernel removes exactly.
+__device__ __forceinline__ int col_shift(const double* __restrict__ C, int K, int b) {
+  double m = 0.0;
+  for (int k = 0; k < K; ++k) m = fmax(m, fmax(fabs(C[2 * (b * K + k)]), fabs(C[2 * (b * K + k) + 1])));
+  if (!(m > 0.0) || !isfinite(m)) return 0;
+  int e;
+  frexp(m, &e);   // m < 2^e
+  return 11 - e;
+}
+
 // Expanded coupling block [[Cr, Ci], [-Ci, Cr]] as KP x 2B operands, column
-// b (< B) = real part of start b, column B + b = imaginary part.
+// b (< B) = real part of start b, column B + b = imaginary part.  The
+// couplings enter every event's sum coherently, so a rounding of C biases
+// all N_D logarithms alike (the error grows like N_D times the gradient);
+// the accurate formats therefore carry C as a sum of parts: FP32 hi + lo,
+// or three FP16 parts (with the column scale above) for the split format.
 template <int FMT>
 __global__ void coupling_kernel(const double* __restrict__ C, int K, int KP, int B, void* out_hi,
-                                void* out_lo) {
+                                void* out_lo, void* out_lo2) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= KP * 2 * B) return;
   const int row = idx / (2 * B), col = idx % (2 * B);
@@ -148,13 +166,21 @@ __global__ void coupling_kernel(const double* __restrict__ C, int K, int KP, int
   if constexpr (FMT == PWA_OP_F64) {
     ((double*)out_hi)[idx] = v;
   } else if constexpr (FMT == PWA_OP_F32) {
-    ((float*)out_hi)[idx] = (float)v;
+    const float h = (float)v;
+    ((float*)out_hi)[idx] = h;
+    ((float*)out_lo)[idx] = (float)(v - (double)h);
   } else if constexpr (FMT == PWA_OP_BF16) {
     ((__bf16*)out_hi)[idx] = (__bf16)(float)v;
+  } else if constexpr (FMT == PWA_OP_F16) {
+    ((_Float16*)out_hi)[idx] = (_Float16)v;
   } else {
+    v = ldexp(v, col_shift(C, K, b));
     const _Float16 h = (_Float16)v;
+    const double r = v - (double)h;
+    const _Float16 l = (_Float16)r;
     ((_Float16*)out_hi)[idx] = h;
-    if constexpr (FMT == PWA_OP_F16X3) ((_Float16*)out_lo)[idx] = (_Float16)(v - (double)h);
+    ((_Float16*)out_lo)[idx] = l;
+    ((_Float16*)out_lo2)[idx] = (_Float16)(r - (double)l);
   }
 }
 
@@ -169,6 +195,11 @@ __global__ void coupling_kernel(const double* __restrict__ C, int K, int KP, int
 // l%16, rows 4 (l/16) + r (FP32 results) or 4 r + l/16 (FP64 results),
 // r = 0..3.
 // ------------------------------------------------------------------------
+// Number of coupling parts per format (see coupling_kernel).
+__host__ __device__ constexpr int c_parts(int fmt) {
+  return fmt == PWA_OP_F32 ? 2 : (fmt == PWA_OP_F16X3 ? 3 : 1);
+}
+
 template <int FMT> struct Mma;
 template <> struct Mma<PWA_OP_F64> {
   static constexpr int KSTEP = 4, E = 1;
@@ -225,15 +256,33 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a) {
   const int b0 = blockIdx.y * CHB;
   // stage this chunk's coupling columns (real: b0.., imag: B + b0..) in LDS
   extern __shared__ char smem_raw[];
-  T* sC = (T*)smem_raw;                        // [2][KP][CHB] (hi) then (lo) for the split format
+  T* sC = (T*)smem_raw;                        // c_parts(FMT) planes of [2][KP][CHB]
+  constexpr int NCP = c_parts(FMT);
   const int plane = 2 * KP * CHB;
   for (int i = threadIdx.x; i < plane; i += blockDim.x) {
     const int part = i / (KP * CHB), rem = i % (KP * CHB), row = rem / CHB, col = rem % CHB;
     const int64_t g = (int64_t)row * 2 * B + (part ? B : 0) + b0 + col;
     sC[i] = ((const T*)a.C_hi)[g];
-    if constexpr (FMT == PWA_OP_F16X3) sC[plane + i] = ((const T*)a.C_lo)[g];
+    if constexpr (NCP > 1) sC[plane + i] = ((const T*)a.C_lo)[g];
+    if constexpr (NCP > 2) sC[2 * plane + i] = ((const T*)a.C_lo2)[g];
   }
   __syncthreads();
+  // B operands (real and imaginary column) of one coupling part from LDS
+  auto load_b = [&](const T* src, int ro, op_t& br, op_t& bi) {
+    if constexpr (M::E == 1) {
+      br = src[ro];
+      bi = src[KP * CHB + ro];
+    } else {
+      T tr[4], ti[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        tr[e] = src[ro + e * CHB];
+        ti[e] = src[KP * CHB + ro + e * CHB];
+      }
+      __builtin_memcpy(&br, tr, sizeof(op_t));
+      __builtin_memcpy(&bi, ti, sizeof(op_t));
+    }
+  };
 
   const int64_t rows_per_block = (a.n + gridDim.x - 1) / gridDim.x;
   const int64_t r_begin = min(a.n, (int64_t)blockIdx.x * rows_per_block);
@@ -267,36 +316,23 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a) {
       for (int ks = 0; ks < NKS; ++ks) {
         const int ro = (ks * M::KSTEP + kg * M::E) * CHB + t * 16 + col;
         op_t br, bi;
-        if constexpr (M::E == 1) {
-          br = sC[ro];
-          bi = sC[KP * CHB + ro];
-        } else {
-          T tr[4], ti[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            tr[e] = sC[ro + e * CHB];
-            ti[e] = sC[KP * CHB + ro + e * CHB];
+        load_b(sC, ro, br, bi);
+        // smaller parts first into the FP32 accumulator
+        if constexpr (NCP > 1) {
+          op_t blr, bli, b2r, b2i;
+          load_b(sC + plane, ro, blr, bli);
+          if constexpr (NCP > 2) {
+            load_b(sC + 2 * plane, ro, b2r, b2i);
+            zr = M::mma(ah[ks], b2r, zr);
+            zi = M::mma(ah[ks], b2i, zi);
+            zr = M::mma(al[ks], br, zr);
+            zi = M::mma(al[ks], bi, zi);
           }
-          __builtin_memcpy(&br, tr, sizeof(op_t));
-          __builtin_memcpy(&bi, ti, sizeof(op_t));
+          zr = M::mma(ah[ks], blr, zr);
+          zi = M::mma(ah[ks], bli, zi);
         }
         zr = M::mma(ah[ks], br, zr);
         zi = M::mma(ah[ks], bi, zi);
-        if constexpr (FMT == PWA_OP_F16X3) {
-          T lr[4], li[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            lr[e] = sC[plane + ro + e * CHB];
-            li[e] = sC[plane + KP * CHB + ro + e * CHB];
-          }
-          op_t blr, bli;
-          __builtin_memcpy(&blr, lr, sizeof(op_t));
-          __builtin_memcpy(&bli, li, sizeof(op_t));
-          zr = M::mma(ah[ks], blr, zr);
-          zi = M::mma(ah[ks], bli, zi);
-          zr = M::mma(al[ks], br, zr);
-          zi = M::mma(al[ks], bi, zi);
-        }
       }
       // epilogue: product of the 4 mantissas, exponents summed
       if constexpr (FMT == PWA_OP_F64) {
@@ -450,16 +486,38 @@ __global__ void gram_final_kernel(const double* __restrict__ part, int nblocks, 
   }
 }
 
-// NLL_b = -F_b + N_D ln(c_b^H Gm c_b / N_MC): F_b summed over row blocks in
-// order (double-double), G_b by the quadratic form in FP64.
-__global__ void batched_final_kernel(const double* __restrict__ part, int nblocks, int B, int K,
+// Per-start sum of the row-block partials in two fixed-order stages.  Stage
+// 1: block (x, c) adds rows c*rpc .. of starts 64x .. 64x+63 (one start per
+// lane, coalesced over starts).
+__global__ __launch_bounds__(64) void batched_rowsum_kernel(const double* __restrict__ part,
+                                                           int nblocks, int B,
+                                                           double* __restrict__ part2) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= B) return;
+  const int rpc = (nblocks + kBatchChunks - 1) / kBatchChunks;
+  const int r0 = blockIdx.y * rpc, r1 = min(nblocks, r0 + rpc);
+  double h = 0.0, l = 0.0;
+  for (int r = r0; r < r1; ++r)
+    dd_add_b(h, l, part[((int64_t)r * B + b) * 2], part[((int64_t)r * B + b) * 2 + 1]);
+  part2[((int64_t)blockIdx.y * B + b) * 2] = h;
+  part2[((int64_t)blockIdx.y * B + b) * 2 + 1] = l;
+}
+
+// Stage 2 and the likelihood: F_b from the chunk partials in order
+// (double-double), less the column scale of the split format, G_b by the
+// quadratic form in FP64, NLL_b = -F_b + N_D ln(c_b^H Gm c_b / N_MC).
+__global__ void batched_final_kernel(const double* __restrict__ part2, int B, int K,
                                      const double* __restrict__ C, const double* __restrict__ gram,
-                                     double nd, double nm, double* __restrict__ nll) {
+                                     double nd, double nm, int scaled, double* __restrict__ nll) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   double h = 0.0, l = 0.0;
-  for (int r = 0; r < nblocks; ++r)
-    dd_add_b(h, l, part[((int64_t)r * B + b) * 2], part[((int64_t)r * B + b) * 2 + 1]);
+  for (int c = 0; c < kBatchChunks; ++c)
+    dd_add_b(h, l, part2[((int64_t)c * B + b) * 2], part2[((int64_t)c * B + b) * 2 + 1]);
+  if (scaled) {   // remove N_D * 2 shift ln 2 (an exact integer times ln 2 in two parts)
+    const double m = -2.0 * nd * (double)col_shift(C, K, b);
+    dd_add_b(h, l, m * 6.93147180369123816490e-01, m * 1.90821492927058770002e-10);
+  }
   const double F = h + l;
   double G = 0.0;
   for (int k = 0; k < K; ++k) {
@@ -521,7 +579,7 @@ hipError_t launch_batched(int fmt, const BatchArgs& a, int row_blocks, const dou
                           const double* gram, int K, double nd, double nm, double* nll,
                           hipStream_t st) {
   const unsigned cg = (unsigned)((a.KP * 2 * a.B + 255) / 256);
-#define PWA_CP(F) hipLaunchKernelGGL(coupling_kernel<F>, dim3(cg), dim3(256), 0, st, C, K, a.KP, a.B, (void*)a.C_hi, (void*)a.C_lo)
+#define PWA_CP(F) hipLaunchKernelGGL(coupling_kernel<F>, dim3(cg), dim3(256), 0, st, C, K, a.KP, a.B, (void*)a.C_hi, (void*)a.C_lo, (void*)a.C_lo2)
   switch (fmt) {
     case PWA_OP_F64: PWA_CP(PWA_OP_F64); break;
     case PWA_OP_F32: PWA_CP(PWA_OP_F32); break;
@@ -534,7 +592,7 @@ hipError_t launch_batched(int fmt, const BatchArgs& a, int row_blocks, const dou
   if (e != hipSuccess) return e;
   constexpr int CHB = 64;
   const dim3 grid(row_blocks, (a.B + CHB - 1) / CHB);
-  const size_t lds = (size_t)2 * a.KP * CHB * batched_elem_bytes(fmt) * (fmt == PWA_OP_F16X3 ? 2 : 1);
+  const size_t lds = (size_t)2 * a.KP * CHB * batched_elem_bytes(fmt) * c_parts(fmt);
   const bool wide = (fmt == PWA_OP_F64 || fmt == PWA_OP_F32);
   const int nks = a.KP / (wide ? 4 : 16);
 #define PWA_BK(F, N) hipLaunchKernelGGL((batched_kernel<F, CHB, N>), grid, dim3(256), lds, st, a)
@@ -565,8 +623,12 @@ hipError_t launch_batched(int fmt, const BatchArgs& a, int row_blocks, const dou
 #undef PWA_BK
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batched_final_kernel, dim3((a.B + 255) / 256), dim3(256), 0, st, a.part,
-                     row_blocks, a.B, K, C, gram, nd, nm, nll);
+  hipLaunchKernelGGL(batched_rowsum_kernel, dim3((a.B + 63) / 64, kBatchChunks), dim3(64), 0, st,
+                     a.part, row_blocks, a.B, a.part2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(batched_final_kernel, dim3((a.B + 255) / 256), dim3(256), 0, st, a.part2,
+                     a.B, K, C, gram, nd, nm, fmt == PWA_OP_F16X3 ? 1 : 0, nll);
   return hipGetLastError();
 }
 

@@ -122,6 +122,9 @@ struct FinalArgs {
 hipError_t launch_precompute(const double* s12, const double* s13, int64_t n, int64_t offset,
                              void* planes, int64_t stride, int is_f32, const ModelDev& md,
                              const FieldSpec& fs, hipStream_t st);
+hipError_t launch_intensity(bool f32, const void* planes, int64_t stride, int64_t base, int64_t n,
+                            const double* tbl, const int* itbl, int K, double* out,
+                            hipStream_t st);
 hipError_t launch_table(const double* theta, const double* v, const ModelDev& md, int kslots,
                         double* tbl64, float* tbl32, int* itbl, int* status, hipStream_t st);
 // layout 1: T lanes of one wave share an event; layout 2: T waves of one

@@ -1010,6 +1010,35 @@ __global__ __launch_bounds__(1024) void combine_kernel(int P, int n_shards,
 }
 
 // ------------------------------------------------------------------------
+// Per-event intensity omega(x) = |sum_k c_k beta_k u w_k|^2 (eq. (1)) of n
+// bound events starting at `base`, one event per lane, table rows in
+// resonance order.  Used to draw events from the model (accept-reject).
+// ------------------------------------------------------------------------
+template <typename Real>
+__global__ __launch_bounds__(256) void intensity_kernel(const Real* __restrict__ planes,
+                                                        int64_t stride, int64_t base, int64_t n,
+                                                        const double* __restrict__ tbl,
+                                                        const int* __restrict__ itbl, int K,
+                                                        double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t e = base + i;
+  double zr = 0.0, zi = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double* t = tbl + k * TS;
+    const double s = (double)planes[(int64_t)itbl[k * ITS + 0] * stride + e];
+    const double u = (double)planes[(int64_t)itbl[k * ITS + 1] * stride + e] * t[TB_UMUL] + t[TB_UADD];
+    const double g = (double)planes[(int64_t)itbl[k * ITS + 2] * stride + e];
+    const double Dr = t[TB_M2] - s, Di = t[TB_NGE] * g;
+    const double inv = 1.0 / (Dr * Dr + Di * Di);
+    const double uwr = u * Dr * inv, uwi = -u * Di * inv;
+    zr += t[TB_CBR] * uwr - t[TB_CBI] * uwi;
+    zi += t[TB_CBR] * uwi + t[TB_CBI] * uwr;
+  }
+  out[i] = zr * zr + zi * zi;
+}
+
+// ------------------------------------------------------------------------
 // Launchers and the table of built launch shapes.
 // ------------------------------------------------------------------------
 hipError_t launch_precompute(const double* s12, const double* s13, int64_t n, int64_t offset,
@@ -1023,6 +1052,20 @@ hipError_t launch_precompute(const double* s12, const double* s13, int64_t n, in
   else
     hipLaunchKernelGGL(precompute_kernel<double>, dim3(grid), dim3(256), 0, st, s12, s13, n,
                        offset, (double*)planes, stride, md, fs);
+  return hipGetLastError();
+}
+
+hipError_t launch_intensity(bool f32, const void* planes, int64_t stride, int64_t base, int64_t n,
+                            const double* tbl, const int* itbl, int K, double* out,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (f32)
+    hipLaunchKernelGGL(intensity_kernel<float>, dim3(grid), dim3(256), 0, st, (const float*)planes,
+                       stride, base, n, tbl, itbl, K, out);
+  else
+    hipLaunchKernelGGL(intensity_kernel<double>, dim3(grid), dim3(256), 0, st,
+                       (const double*)planes, stride, base, n, tbl, itbl, K, out);
   return hipGetLastError();
 }
 

@@ -116,6 +116,9 @@ def test_unbound_and_bad_bind_arguments(lib):
         assert lib.pwa_grad(h, fake, fake, fake, st) == L.PWA_E_STATE
         assert lib.pwa_hvp(h, fake, fake, fake, None, None, st) == L.PWA_E_STATE
         assert lib.pwa_partials(h, fake, None, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_intensity(h, fake, 0, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_intensity(h, fake, 2, fake, st) == L.PWA_E_INVALID
+        assert lib.pwa_intensity(h, None, 0, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_device_status(h, st) == L.PWA_E_STATE
         assert lib.pwa_nll(None, fake, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_nll(h, None, fake, st) == L.PWA_E_INVALID
