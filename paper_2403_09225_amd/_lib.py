@@ -1,4 +1,4 @@
-"""ctypes declarations of the C ABI in include/pwa.h.
+"""ctypes declarations of the C ABI in include/pwa.h and include/pwa_mlp.h.
 
 Loading imports torch first so that libpwa.so binds to the HIP runtime torch
 already loaded (both carry the soname libamdhip64.so.7): device pointers and
@@ -42,6 +42,10 @@ class PwaFitOpts(ctypes.Structure):
                 ("free_mask_set", c_int32), ("free_mask", ctypes.c_uint8 * (4 * PWA_MAX_RES))]
 
 
+class PwaMlpDims(ctypes.Structure):
+    _fields_ = [("n_in", c_int32), ("n_h1", c_int32), ("n_h2", c_int32), ("n_out", c_int32)]
+
+
 class PwaFitReport(ctypes.Structure):
     _fields_ = [("nll", c_double), ("grad_max", c_double), ("seconds", c_double),
                 ("iterations", c_int32), ("n_nll", c_int32), ("n_grad", c_int32),
@@ -73,6 +77,19 @@ SIGNATURES = {
     "pwa_freeze": (c_int32, [_P, _P, c_int32, c_int32, _P, c_size_t, _P]),
     "pwa_nll_batched": (c_int32, [_P, _P, c_int32, _P, _P]),
     "pwa_gram": (c_int32, [_P, _P, _P]),
+    # include/pwa_mlp.h
+    "pwa_hist2d": (c_int32, [_P, _P, _P, c_int32, c_double, ctypes.POINTER(c_double), _P, _P]),
+    "pwa_mlp_n_params": (c_int64, [ctypes.POINTER(PwaMlpDims)]),
+    "pwa_mlp_n_transposed": (c_int64, [ctypes.POINTER(PwaMlpDims)]),
+    "pwa_mlp_workspace_bytes": (c_size_t, [ctypes.POINTER(PwaMlpDims), c_int32]),
+    "pwa_mlp_cast": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, _P]),
+    "pwa_mlp_forward": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, c_int32, _P, _P,
+                                  c_size_t, _P]),
+    "pwa_mlp_backward": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, c_int32, _P, c_size_t,
+                                   _P, _P, _P]),
+    "pwa_mlp_adam": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, _P, c_int32, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               _P, _P, _P]),
 }
 
 _lib = None

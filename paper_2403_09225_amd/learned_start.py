@@ -1,0 +1,438 @@
+"""Learned start-point proposal for Newton-CG fits.
+
+The paper fits from random start points and counts how many fits reach the
+global minimum (Sec. 3, the fit-success study: a few per cent to about a
+third of random starts, depending on the convergence tolerance).  Here a
+small network maps the binned data of a fit -- a 32 x 32 histogram of the
+events over the Dalitz plane -- to a start point.  It is trained on fits that
+the likelihood library performs on toy data drawn from the model, with
+random multi-start as the fallback and the exact NLL deciding success.
+
+Everything runs on the GPU through the library: toys (accept-reject on the
+per-event intensity), histograms (pwa_hist2d), fits (pwa_fit), and the MLP's
+forward pass, backward pass and Adam step (pwa_mlp_*, bfloat16 matrix cores
+with FP32 master weights).
+
+Parameter coding.  The NLL is invariant under a global phase and scale of
+the couplings (eq. (3): the normalisation divides out |c|^2) and resonances
+with the same channel and spin are interchangeable, so a label is made
+canonical before it is learned: such resonances are ordered by mass, the
+couplings are rotated so that c_0 is real positive and scaled to unit
+r.m.s. modulus, and M, Gamma are mapped affinely from the prior's ranges
+onto [-1, 1].
+"""
+
+import ctypes
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .api import DAUGHTER_MASSES, PARENT_MASS, Likelihood, _ptr, _stream
+from .toys import ToyGenerator
+
+NBINS = 32
+PAIRS = ((0, 1), (0, 2), (1, 2))     # daughters of channels (12), (13), (23)
+
+# prior of the random starts (and of the toys' true parameters)
+M_RANGE = (0.6, 1.6)
+G_RANGE = (0.03, 0.3)
+C_RANGE = (0.2, 1.0)
+
+
+def threshold(ch, masses=DAUGHTER_MASSES):
+    a, b = PAIRS[ch]
+    return masses[a] + masses[b]
+
+
+def draw_start(channel, rng, masses=DAUGHTER_MASSES):
+    """Random parameters from the prior: M ~ U(M_RANGE) above the channel
+    threshold + 20 MeV, Gamma ~ U(G_RANGE), |c| ~ U(C_RANGE), uniform phase."""
+    th = np.empty(4 * len(channel))
+    for k, ch in enumerate(channel):
+        m = rng.uniform(*M_RANGE)
+        while m < threshold(ch, masses) + 0.02:
+            m = rng.uniform(*M_RANGE)
+        g = rng.uniform(*G_RANGE)
+        mag, ph = rng.uniform(*C_RANGE), rng.uniform(0.0, 2.0 * np.pi)
+        th[4 * k:4 * k + 4] = (mag * np.cos(ph), mag * np.sin(ph), m, g)
+    return th
+
+
+class StartCoder:
+    """Canonical form and the affine coding of parameter vectors."""
+
+    def __init__(self, channel, spin, masses=DAUGHTER_MASSES):
+        self.channel, self.spin = list(channel), list(spin)
+        self.K = len(channel)
+        self.P = 4 * self.K
+        groups = {}
+        for k, key in enumerate(zip(channel, spin)):
+            groups.setdefault(key, []).append(k)
+        self.groups = [g for g in groups.values() if len(g) > 1]
+        self.thr = np.array([threshold(c, masses) for c in channel])
+
+    def canonical(self, theta):
+        th = np.asarray(theta, dtype=np.float64).reshape(self.K, 4).copy()
+        for g in self.groups:
+            order = sorted(g, key=lambda k: th[k, 2])
+            th[g] = th[order]
+        c = th[:, 0] + 1j * th[:, 1]
+        if abs(c[0]) > 0:
+            c = c * np.exp(-1j * np.angle(c[0]))
+        rms = np.sqrt(np.mean(np.abs(c) ** 2))
+        if rms > 0:
+            c = c / rms
+        th[:, 0], th[:, 1] = c.real, c.imag
+        return th.reshape(-1)
+
+    def encode(self, theta):
+        th = self.canonical(theta).reshape(self.K, 4)
+        y = th.copy()
+        y[:, 2] = (th[:, 2] - 0.5 * sum(M_RANGE)) / (0.5 * (M_RANGE[1] - M_RANGE[0]))
+        y[:, 3] = (th[:, 3] - 0.5 * sum(G_RANGE)) / (0.5 * (G_RANGE[1] - G_RANGE[0]))
+        return y.reshape(-1)
+
+    def decode(self, y):
+        y = np.asarray(y, dtype=np.float64).reshape(self.K, 4)
+        th = y.copy()
+        th[:, 2] = 0.5 * sum(M_RANGE) + 0.5 * (M_RANGE[1] - M_RANGE[0]) * y[:, 2]
+        th[:, 3] = 0.5 * sum(G_RANGE) + 0.5 * (G_RANGE[1] - G_RANGE[0]) * y[:, 3]
+        th[:, 2] = np.maximum(th[:, 2], self.thr + 0.02)
+        th[:, 3] = np.clip(th[:, 3], 0.5 * G_RANGE[0], 2.0 * G_RANGE[1])
+        c = th[:, 0] + 1j * th[:, 1]
+        if not np.all(np.abs(c) > 1e-3):     # keep every coupling alive
+            c = np.where(np.abs(c) > 1e-3, c, 1e-3)
+        th[:, 0], th[:, 1] = c.real, c.imag
+        return th.reshape(-1)
+
+
+def histograms(s12, s13, offsets, parent=PARENT_MASS, masses=DAUGHTER_MASSES):
+    """Normalised 32 x 32 Dalitz histograms of event sets (pwa_hist2d).
+    s12, s13: FP64 device tensors; offsets: n_sets + 1 int64 boundaries."""
+    lib = L.load()
+    s12 = s12.to(dtype=torch.float64).contiguous()
+    s13 = s13.to(dtype=torch.float64).contiguous()
+    off = torch.as_tensor(offsets, dtype=torch.int64, device=s12.device).contiguous()
+    n_sets = int(off.numel()) - 1
+    out = torch.empty(n_sets, NBINS * NBINS, dtype=torch.float32, device=s12.device)
+    m = (ctypes.c_double * 3)(*masses)
+    L.check("pwa_hist2d", lib.pwa_hist2d(_ptr(s12), _ptr(s13), _ptr(off), n_sets, parent, m,
+                                         _ptr(out), _stream()))
+    return out
+
+
+class MLP:
+    """n_in -> n_h1 -> n_h2 -> n_out with GELU, trained with Adam in bf16 on
+    the matrix cores (FP32 master weights and moments)."""
+
+    def __init__(self, dims=(1024, 512, 512, 48), seed=0, device="cuda"):
+        self.lib = L.load()
+        self.dims = L.PwaMlpDims(*dims)
+        self.n_in, self.n_h1, self.n_h2, self.n_out = dims
+        self.device = torch.device(device)
+        n = int(self.lib.pwa_mlp_n_params(ctypes.byref(self.dims)))
+        if n == 0:
+            raise ValueError("layer widths n_in, n_h1, n_h2 must be multiples of 16")
+        self.n_params = n
+        g = torch.Generator(device="cpu")
+        g.manual_seed(seed)
+        parts = []
+        for fan_out, fan_in, gain in ((self.n_h1, self.n_in, 2.0), (self.n_h2, self.n_h1, 2.0),
+                                      (self.n_out, self.n_h2, 1.0)):
+            parts.append(torch.randn(fan_out * fan_in, generator=g) * np.sqrt(gain / fan_in))
+            parts.append(torch.zeros(fan_out))
+        self.w = torch.cat(parts).to(device=self.device, dtype=torch.float32).contiguous()
+        assert self.w.numel() == n
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.wbf = torch.empty(n, dtype=torch.int16, device=self.device)
+        nt = int(self.lib.pwa_mlp_n_transposed(ctypes.byref(self.dims)))
+        self.wtbf = torch.empty(nt, dtype=torch.int16, device=self.device)
+        self.step = 0
+        self._ws, self._ws_batch = None, 0
+        self.cast()
+
+    def cast(self):
+        L.check("pwa_mlp_cast", self.lib.pwa_mlp_cast(ctypes.byref(self.dims), _ptr(self.w),
+                                                      _ptr(self.wbf), _ptr(self.wtbf), _stream()))
+
+    def _workspace(self, batch):
+        nb = int(self.lib.pwa_mlp_workspace_bytes(ctypes.byref(self.dims), batch))
+        if self._ws is None or self._ws.numel() < nb + 256:
+            self._ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        return ctypes.c_void_p(self._ws.data_ptr() + off), nb
+
+    def forward(self, x):
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        B = int(x.shape[0])
+        ws, nb = self._workspace(B)
+        y = torch.empty(B, self.n_out, dtype=torch.float32, device=self.device)
+        L.check("pwa_mlp_forward", self.lib.pwa_mlp_forward(
+            ctypes.byref(self.dims), _ptr(self.w), _ptr(self.wbf), _ptr(x), B, _ptr(y), ws, nb,
+            _stream()))
+        return y
+
+    def loss_grad(self, x, t):
+        """Loss (FP64 scalar tensor) and gradient (packed FP32) on a batch."""
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device).contiguous()
+        t = torch.as_tensor(t, dtype=torch.float32, device=self.device).contiguous()
+        y = self.forward(x)
+        B = int(x.shape[0])
+        ws, nb = self._workspace(B)
+        grad = torch.empty_like(self.w)
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        L.check("pwa_mlp_backward", self.lib.pwa_mlp_backward(
+            ctypes.byref(self.dims), _ptr(self.wtbf), _ptr(y), _ptr(t), B, ws, nb, _ptr(grad),
+            _ptr(loss), _stream()))
+        return loss[0], grad
+
+    def adam(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        self.step += 1
+        L.check("pwa_mlp_adam", self.lib.pwa_mlp_adam(
+            ctypes.byref(self.dims), _ptr(self.w), _ptr(self.m), _ptr(self.v), _ptr(grad),
+            self.step, lr, beta1, beta2, eps, weight_decay, _ptr(self.wbf), _ptr(self.wtbf),
+            _stream()))
+
+    def loss(self, x, t):
+        """Mean-squared error of the network on (x, t) (forward only)."""
+        t = torch.as_tensor(t, dtype=torch.float32, device=self.device)
+        return float(((self.forward(x) - t) ** 2).mean())
+
+    def train(self, x, t, epochs=100, batch=256, lr=1e-3, seed=0, lr_end=None,
+              weight_decay=0.0, x_val=None, t_val=None):
+        """Mini-batch Adam over (x, t); returns the per-epoch mean losses.
+        With a validation set, the weights of the epoch with the lowest
+        validation loss are kept (early stopping)."""
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.device)
+        t = torch.as_tensor(t, dtype=torch.float32, device=self.device)
+        n = int(x.shape[0])
+        g = torch.Generator(device="cpu")
+        g.manual_seed(seed)
+        hist = []
+        self.val_history = []
+        best = (float("inf"), None)
+        for ep in range(epochs):
+            rate = lr if lr_end is None else lr * (lr_end / lr) ** (ep / max(1, epochs - 1))
+            perm = torch.randperm(n, generator=g).to(self.device)
+            tot = []
+            for i in range(0, n - batch + 1 if n >= batch else 1, batch):
+                idx = perm[i:i + batch]
+                loss, grad = self.loss_grad(x[idx], t[idx])
+                self.adam(grad, lr=rate, weight_decay=weight_decay)
+                tot.append(loss)
+            hist.append(float(torch.stack(tot).mean()))
+            if x_val is not None:
+                v = self.loss(x_val, t_val)
+                self.val_history.append(v)
+                if v < best[0]:
+                    best = (v, self.w.clone())
+        if best[1] is not None:
+            self.w.copy_(best[1])
+            self.cast()
+        return hist
+
+
+# ---------------------------------------------------------------------------
+# Toy fits: training data and evaluation.
+# ---------------------------------------------------------------------------
+def fit(lik, start, xtol=1e-6, maxiter=100, time_cap_s=5.0):
+    th, rep = lik.fit(start, xtol=xtol, maxiter=maxiter, time_cap_s=time_cap_s)
+    return th.cpu().numpy(), rep
+
+
+class ToyStudy:
+    """Toys of one resonance layout with a shared MC sample."""
+
+    def __init__(self, channel, spin, n_mc, seed=0, device="cuda"):
+        self.channel, self.spin = list(channel), list(spin)
+        self.coder = StartCoder(channel, spin)
+        self.gen = torch.Generator(device=device)
+        self.gen.manual_seed(seed)
+        self.rng = np.random.Generator(np.random.PCG64(seed))
+        self.toys = ToyGenerator(channel, spin, batch=1 << 19, scan=1 << 18, device=device)
+        from .toys import uniform_dalitz
+        self.mc = uniform_dalitz(n_mc, self.gen, device=device)
+        self.device = device
+
+    def toy(self, n_events):
+        """(true canonical theta, events) of one toy."""
+        th = self.coder.canonical(draw_start(self.channel, self.rng))
+        ev = self.toys.draw(th, n_events, self.gen)
+        return th, ev
+
+    def likelihood(self, ev):
+        lik = Likelihood(self.channel, self.spin, device=self.device)
+        return lik.bind(ev[0], ev[1], self.mc[0], self.mc[1])
+
+    def features(self, ev, n_events):
+        """Network input of one event set: its histogram scaled by the bin
+        count (a flat distribution over the box gives 1 per bin)."""
+        return histograms(ev[0], ev[1], [0, n_events]) * float(NBINS * NBINS)
+
+    def resampled_features(self, ev, n_events, n_rep):
+        """Features of n_rep bootstrap resamples of one event set (the
+        statistical fluctuation of a toy of the same size), for augmentation."""
+        idx = torch.randint(0, n_events, (n_rep * n_events,), generator=self.gen,
+                            device=ev[0].device)
+        off = torch.arange(0, n_rep + 1, dtype=torch.int64, device=ev[0].device) * n_events
+        return histograms(ev[0][idx], ev[1][idx], off) * float(NBINS * NBINS)
+
+    def training_set(self, n_toys, n_events, log_every=0, label_bound=4.0, n_rep=0):
+        """Features and coded labels of toy fits started at the truth.  Fits
+        that do not converge, or end with a coded parameter beyond
+        +-label_bound (a resonance the toy does not constrain wandering off),
+        are left out.  With n_rep > 0, each toy also contributes n_rep
+        bootstrap resamples of its events with the same label; the toy index
+        of every row is returned so that a validation split can keep whole
+        toys apart."""
+        hs, ys, ids = [], [], []
+        t0 = time.time()
+        for i in range(n_toys):
+            th, ev = self.toy(n_events)
+            lik = self.likelihood(ev)
+            th_fit, rep = fit(lik, th)
+            if not np.all(np.isfinite(th_fit)) or not rep["converged"]:
+                continue
+            y = self.coder.encode(th_fit)
+            if np.max(np.abs(y)) > label_bound:
+                continue
+            f = self.features(ev, n_events)
+            if n_rep:
+                f = torch.cat([f, self.resampled_features(ev, n_events, n_rep)])
+            hs.append(f)
+            ys.extend([y] * int(f.shape[0]))
+            ids.extend([i] * int(f.shape[0]))
+            if log_every and (i + 1) % log_every == 0:
+                print(f"[learned-start] {i + 1}/{n_toys} toy fits, {time.time() - t0:.1f} s",
+                      flush=True)
+        x = torch.cat(hs)
+        y = torch.as_tensor(np.stack(ys), dtype=torch.float32, device=self.device)
+        return x, y, np.asarray(ids)
+
+    def propose(self, net, hists):
+        y = net.forward(hists).cpu().numpy().astype(np.float64)
+        return [self.coder.decode(r) for r in y]
+
+    def evaluate(self, net, n_toys, n_events, n_random, tol=0.01, log_every=0):
+        """Proposal-started fits against random multi-start on held-out toys.
+
+        Per toy, NLL_min is the lowest NLL of all its fits (from the truth,
+        the proposal and every random start); a fit succeeds when its NLL is
+        within `tol` of it.  Random multi-start is priced as the expected
+        cost until its first success over a random order of its starts
+        (failures before the first success count in full); the proposal
+        strategy costs its own fit plus, when that fails, the random
+        strategy's expected cost."""
+        rows = []
+        t0 = time.time()
+        for i in range(n_toys):
+            th, ev = self.toy(n_events)
+            lik = self.likelihood(ev)
+            start = self.propose(net, self.features(ev, n_events))[0]
+            fits = {"truth": fit(lik, th), "proposal": fit(lik, start)}
+            rnd = [fit(lik, draw_start(self.channel, self.rng)) for _ in range(n_random)]
+            nlls = [f[1]["nll"] for f in list(fits.values()) + rnd]
+            nmin = min(x for x in nlls if np.isfinite(x))
+            ok = lambda rep: np.isfinite(rep["nll"]) and rep["nll"] <= nmin + tol  # noqa: E731
+            succ = [ok(r[1]) for r in rnd]
+            S = sum(succ)
+
+            def expected(key):
+                costs = [r[1][key] for r in rnd]
+                if S == 0:
+                    return float(sum(costs)), False
+                fail = sum(c for c, s in zip(costs, succ) if not s)
+                good = sum(c for c, s in zip(costs, succ) if s)
+                return fail / (S + 1) + good / S, True
+
+            p_ok = ok(fits["proposal"][1])
+            row = {"proposal_success": bool(p_ok), "random_success_fraction": S / max(1, n_random)}
+            for key in ("iterations", "seconds"):
+                e_rnd, found = expected(key)
+                row[f"random_{key}"] = e_rnd
+                row["random_found"] = found
+                row[f"proposal_{key}"] = fits["proposal"][1][key] + (0.0 if p_ok else e_rnd)
+            rows.append(row)
+            if log_every and (i + 1) % log_every == 0:
+                print(f"[learned-start] evaluated {i + 1}/{n_toys} toys, {time.time() - t0:.1f} s",
+                      flush=True)
+        summary = {
+            "toys": n_toys, "events_per_toy": n_events, "random_starts": n_random, "tol": tol,
+            "proposal_success_rate": float(np.mean([r["proposal_success"] for r in rows])),
+            "random_start_success_rate": float(np.mean([r["random_success_fraction"] for r in rows])),
+            "mean_iterations_proposal_strategy": float(np.mean([r["proposal_iterations"] for r in rows])),
+            "mean_iterations_random_strategy": float(np.mean([r["random_iterations"] for r in rows])),
+            "mean_seconds_proposal_strategy": float(np.mean([r["proposal_seconds"] for r in rows])),
+            "mean_seconds_random_strategy": float(np.mean([r["random_seconds"] for r in rows])),
+        }
+        return summary, rows
+
+
+def resonance_layout(K):
+    """Resonance k in channel k mod 3 with spin floor(k / 3) mod 3."""
+    return [k % 3 for k in range(K)], [(k // 3) % 3 for k in range(K)]
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="Train and evaluate the start-point proposal")
+    ap.add_argument("--K", type=int, default=12)
+    ap.add_argument("--train", type=int, default=2000, help="training toys")
+    ap.add_argument("--events", type=int, default=20000, help="events per training toy")
+    ap.add_argument("--mc", type=int, default=200000)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--rep", type=int, default=4, help="bootstrap resamples per training toy")
+    ap.add_argument("--wd", type=float, default=1e-4, help="decoupled weight decay")
+    ap.add_argument("--val", type=float, default=0.1, help="fraction of toys held for validation")
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval", type=int, default=40, help="held-out toys")
+    ap.add_argument("--eval-events", type=int, default=100000)
+    ap.add_argument("--random", type=int, default=32, help="random starts per held-out toy")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+    ch, sp = resonance_layout(a.K)
+    t0 = time.time()
+    study = ToyStudy(ch, sp, a.mc, seed=a.seed)
+    x, y, ids = study.training_set(a.train, a.events, log_every=max(1, a.train // 10), n_rep=a.rep)
+    t_data = time.time() - t0
+    toys = np.unique(ids)
+    n_val = int(round(a.val * len(toys)))
+    val_toys = set(np.random.Generator(np.random.PCG64(a.seed)).choice(toys, n_val, replace=False))
+    is_val = torch.as_tensor([i in val_toys for i in ids], device=x.device)
+    xv, yv = x[is_val], y[is_val]
+    x, y = x[~is_val], y[~is_val]
+    net = MLP((NBINS * NBINS, 512, 512, 4 * a.K), seed=a.seed)
+    t1 = time.time()
+    yc = y.cpu().numpy()
+    print(f"[learned-start] {x.shape[0]} labels: mean |y| {np.mean(np.abs(yc)):.3f}, "
+          f"std {yc.std():.3f}, max |y| {np.max(np.abs(yc)):.3f}", flush=True)
+    losses = net.train(x, y, epochs=a.epochs, batch=min(a.batch, int(x.shape[0])), lr=a.lr,
+                       lr_end=a.lr * 0.05, seed=a.seed, weight_decay=a.wd,
+                       x_val=xv if n_val else None, t_val=yv if n_val else None)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    vh = net.val_history
+    print(f"[learned-start] trained: loss {losses[0]:.4f} -> {losses[-1]:.4f}; validation "
+          f"{vh[0] if vh else float('nan'):.4f} -> best {min(vh) if vh else float('nan'):.4f} "
+          f"(epoch {int(np.argmin(vh)) + 1 if vh else 0})", flush=True)
+    ev = ToyStudy(ch, sp, a.mc, seed=a.seed + 1000)
+    summary, _ = ev.evaluate(net, a.eval, a.eval_events, a.random, log_every=max(1, a.eval // 10))
+    summary.update({"K": a.K, "train_toys": int(len(toys) - n_val), "val_toys": n_val,
+                    "train_rows": int(x.shape[0]), "train_events": a.events, "mc": a.mc,
+                    "epochs": a.epochs, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
+                    "val_loss_best": min(vh) if vh else None,
+                    "seconds_training_set": round(t_data, 1), "seconds_training": round(t_train, 1)})
+    print(json.dumps(summary), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(summary, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,9 +20,13 @@ def lib():
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "pwa.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pwa_\w+)\s*\(", text)))
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, f)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(pwa_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def _model(K=2, channel=None, spin=None):
@@ -156,3 +160,27 @@ def test_status_strings(lib):
         s = lib.pwa_status_str(code)
         assert s and len(s) >= 2
     assert b"unknown" in lib.pwa_status_str(-99)
+
+
+def test_mlp_host_validation(lib):
+    d = L.PwaMlpDims(1024, 512, 512, 48)
+    assert lib.pwa_mlp_n_params(ctypes.byref(d)) == 512 * 1024 + 512 + 512 * 512 + 512 + 48 * 512 + 48
+    assert lib.pwa_mlp_n_transposed(ctypes.byref(d)) == 512 * 512 + 512 * 48
+    bad = L.PwaMlpDims(1000, 512, 512, 48)
+    assert lib.pwa_mlp_n_params(ctypes.byref(bad)) == 0
+    assert lib.pwa_mlp_workspace_bytes(ctypes.byref(bad), 16) == 0
+    nb = lib.pwa_mlp_workspace_bytes(ctypes.byref(d), 100)
+    assert nb > 0 and nb == lib.pwa_mlp_workspace_bytes(ctypes.byref(d), 112)
+    fake = ctypes.c_void_p(0x1000)
+    st = None
+    assert lib.pwa_mlp_forward(ctypes.byref(d), fake, fake, None, 4, fake, fake, nb, st) == L.PWA_E_INVALID
+    assert lib.pwa_mlp_forward(ctypes.byref(d), fake, fake, fake, 0, fake, fake, nb, st) == L.PWA_E_INVALID
+    assert lib.pwa_mlp_forward(ctypes.byref(d), fake, fake, fake, 4, fake, fake, 16, st) == L.PWA_E_WORKSPACE
+    assert lib.pwa_mlp_backward(ctypes.byref(bad), fake, fake, fake, 4, fake, nb, fake, fake, st) == L.PWA_E_INVALID
+    assert lib.pwa_mlp_adam(ctypes.byref(d), fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8,
+                            0.0, fake, fake, st) == L.PWA_E_INVALID
+    assert lib.pwa_mlp_adam(ctypes.byref(d), fake, fake, fake, fake, 1, 1e-3, 0.9, 0.999, 1e-8,
+                            -1.0, fake, fake, st) == L.PWA_E_INVALID
+    masses = (ctypes.c_double * 3)(0.494, 0.140, 0.140)
+    assert lib.pwa_hist2d(fake, fake, fake, 0, 1.865, masses, fake, st) == L.PWA_E_INVALID
+    assert lib.pwa_hist2d(fake, fake, fake, 1, 0.5, masses, fake, st) == L.PWA_E_INVALID

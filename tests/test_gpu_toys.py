@@ -59,7 +59,7 @@ def test_toys_follow_the_intensity():
     tg = ToyGenerator(W.channel, W.spin, batch=1 << 20, scan=1 << 18)
     s12, s13 = tg.draw(W.theta_true, n, gen)
     s12, s13 = s12.cpu().numpy(), s13.cpu().numpy()
-    assert s12.shape == (n,) and np.all(synth.inside(s12, s13))
+    assert s12.shape == (n,) and np.all(synth.events.inside(s12, s13))
     # expected bin contents from the oracle's intensity on uniform events
     mc = synth.uniform_phase_space(2_000_000, rng(77))
     w = oracle.intensity(mc, model, W.theta_true)
