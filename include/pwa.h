@@ -121,7 +121,9 @@ size_t pwa_workspace_bytes(const pwa_ctx* ctx, int64_t n_data, int64_t n_mc);
  * arrays are read on `stream` during this call and not retained.
  * d_ws: caller-owned device buffer of ws_bytes >= pwa_workspace_bytes(),
  * 256-byte aligned; it must stay allocated while the context is used.
- * n_data >= 0, n_mc >= 1.
+ * n_data >= 0, n_mc >= 1, n_data + n_mc <= 2^29 - 64 (536 870 848) events
+ * per context (larger samples are sharded over contexts and combined with
+ * pwa_partials / pwa_combine).
  * Errors: PWA_E_INVALID (null pointers, sizes), PWA_E_WORKSPACE, PWA_E_HIP. */
 int pwa_bind(pwa_ctx* ctx, const double* d_s12, const double* d_s13, int64_t n_data,
              const double* d_mc_s12, const double* d_mc_s13, int64_t n_mc,
@@ -178,9 +180,11 @@ int pwa_combine(int32_t n_par, int32_t n_shards, const double* d_parts,
 
 /* Newton-CG fit options (host memory). */
 typedef struct pwa_fit_opts {
-  double xtol;            /* stop when mean |step| <= xtol (scipy's rule)      */
+  double xtol;            /* stop when mean |step| <= xtol (scipy's rule); a
+                             Newton step within it ends the fit before its
+                             line search (the NLL is flat to rounding there) */
   int32_t maxiter;        /* outer Newton iterations (<= 0: 200)              */
-  int32_t cg_maxiter;     /* CG iterations per Newton step (<= 0: 2P)          */
+  int32_t cg_maxiter;     /* CG iterations per Newton step (<= 0: 20 P)        */
   double time_cap_s;      /* wall-clock cap, seconds (<= 0: none); Sec. 3 uses 500 */
   int32_t hvp_precision;  /* pwa_precision of the HVPs inside CG              */
   int32_t free_mask_set;  /* 0: all parameters free; 1: use free_mask         */

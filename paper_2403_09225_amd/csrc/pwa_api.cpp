@@ -329,9 +329,13 @@ void pwa_destroy(pwa_ctx* c) { delete c; }
 
 int32_t pwa_n_par(const pwa_ctx* c) { return c ? c->P : -1; }
 
+// Events per context: every plane of the event stream is addressed with a
+// 32-bit byte offset, so its padded length is limited to 2^32 bytes in FP64.
+constexpr int64_t kMaxEvents = ((int64_t)1 << 29) - 64;
+
 size_t pwa_workspace_bytes(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
   if (!c || n_data < 0 || n_mc < 1) return 0;
-  if (n_data > ((int64_t)1 << 40) || n_mc > ((int64_t)1 << 40)) return 0;
+  if (n_data + n_mc > kMaxEvents) return 0;
   return layout_of(c, n_data, n_mc).total;
 }
 
@@ -341,7 +345,7 @@ int pwa_bind(pwa_ctx* c, const double* d_s12, const double* d_s13, int64_t n_dat
   if (!c || n_data < 0 || n_mc < 1) return PWA_E_INVALID;
   if (n_data > 0 && (!d_s12 || !d_s13)) return PWA_E_INVALID;
   if (!d_mc_s12 || !d_mc_s13) return PWA_E_INVALID;
-  if (n_data > ((int64_t)1 << 40) || n_mc > ((int64_t)1 << 40)) return PWA_E_INVALID;
+  if (n_data > kMaxEvents || n_mc > kMaxEvents || n_data + n_mc > kMaxEvents) return PWA_E_INVALID;
   if (!d_ws || ((uintptr_t)d_ws % 256) != 0) return PWA_E_WORKSPACE;
   const Layout L = layout_of(c, n_data, n_mc);
   if (ws_bytes < L.total) return PWA_E_WORKSPACE;
@@ -748,7 +752,10 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
       ++i;
       dri0 = dri1;
     }
-    if (sum_abs(xs) == 0.0) {  // already stationary
+    // A Newton step already within the tolerance ends the fit here: at the
+    // minimum the NLL is flat to rounding, and a line search along such a
+    // step can find no decrease.
+    if (sum_abs(xs) <= P * o->xtol) {
       converged = 1;
       break;
     }

@@ -53,9 +53,13 @@ __device__ __forceinline__ double ln_small(float m) {
   const bool lo = f < 0.70710678f;
   f = lo ? 2.0f * f : f;
   e = lo ? e - 1 : e;
-  float r = __builtin_amdgcn_rcpf(f + 1.0f);
-  r = fmaf(r, fmaf(-(f + 1.0f), r, 1.0f), r);
-  const float y = (f - 1.0f) * r;
+  // y = (f - 1)/(f + 1): hardware reciprocal, then one correction of the
+  // quotient from its exact residual (a Newton step on the reciprocal alone
+  // leaves a one-signed error that would bias the log sum).
+  const float fp1 = f + 1.0f, fm1 = f - 1.0f;
+  const float r = __builtin_amdgcn_rcpf(fp1);
+  const float y0 = fm1 * r;
+  const float y = fmaf(fmaf(-y0, fp1, fm1), r, y0);
   const float y2 = y * y;
   float p = fmaf(y2, 1.0f / 9.0f, 1.0f / 7.0f);
   p = fmaf(p, y2, 1.0f / 5.0f);
@@ -312,25 +316,46 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       acc_t zr = {0, 0, 0, 0}, zi = {0, 0, 0, 0};
+      // Accumulate the products smallest-first over the whole inner
+      // dimension: the low parts of C (and A) carry a systematic correction
+      // of relative size 2^-22 .. 2^-24; added step by step to an accumulator
+      // that already holds the large partial sums they would fall below half
+      // an ulp and be dropped every time.
+      if constexpr (NCP > 2) {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+          const int ro = (ks * M::KSTEP + kg * M::E) * CHB + t * 16 + col;
+          op_t br, bi;
+          load_b(sC + 2 * plane, ro, br, bi);
+          zr = M::mma(ah[ks], br, zr);
+          zi = M::mma(ah[ks], bi, zi);
+        }
+      }
+      if constexpr (FMT == PWA_OP_F16X3) {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+          const int ro = (ks * M::KSTEP + kg * M::E) * CHB + t * 16 + col;
+          op_t br, bi;
+          load_b(sC, ro, br, bi);
+          zr = M::mma(al[ks], br, zr);
+          zi = M::mma(al[ks], bi, zi);
+        }
+      }
+      if constexpr (NCP > 1) {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+          const int ro = (ks * M::KSTEP + kg * M::E) * CHB + t * 16 + col;
+          op_t br, bi;
+          load_b(sC + plane, ro, br, bi);
+          zr = M::mma(ah[ks], br, zr);
+          zi = M::mma(ah[ks], bi, zi);
+        }
+      }
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
         const int ro = (ks * M::KSTEP + kg * M::E) * CHB + t * 16 + col;
         op_t br, bi;
         load_b(sC, ro, br, bi);
-        // smaller parts first into the FP32 accumulator
-        if constexpr (NCP > 1) {
-          op_t blr, bli, b2r, b2i;
-          load_b(sC + plane, ro, blr, bli);
-          if constexpr (NCP > 2) {
-            load_b(sC + 2 * plane, ro, b2r, b2i);
-            zr = M::mma(ah[ks], b2r, zr);
-            zi = M::mma(ah[ks], b2i, zi);
-            zr = M::mma(al[ks], br, zr);
-            zi = M::mma(al[ks], bi, zi);
-          }
-          zr = M::mma(ah[ks], blr, zr);
-          zi = M::mma(ah[ks], bli, zi);
-        }
         zr = M::mma(ah[ks], br, zr);
         zi = M::mma(ah[ks], bi, zi);
       }

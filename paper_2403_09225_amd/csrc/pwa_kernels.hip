@@ -89,6 +89,17 @@ __device__ __forceinline__ double log_r(double x) {
   const double de = (double)e;
   return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, r));
 }
+// a * b + c as a multiply and an add (no contraction): when a and c are both
+// wave-uniform scalars, a fused form would need one of them copied to a
+// vector register first (one scalar operand per VALU instruction).
+__device__ __forceinline__ double mad_nc(double a, double b, double c) {
+#pragma clang fp contract(off)
+  return a * b + c;
+}
+__device__ __forceinline__ float mad_nc(float a, float b, float c) {
+#pragma clang fp contract(off)
+  return a * b + c;
+}
 __device__ __forceinline__ double fma_r(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
 // FP64 accumulation of per-event terms (converted once for the FP32 path).
@@ -396,12 +407,20 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
         g_[r] = pg[r][ev];
       }
     } else {
+      // wave-uniform plane bases + one 32-bit byte offset (the stride is
+      // limited to 2^32 bytes per plane at bind time)
       c_int* it = opaque_s((c_int*)a.itbl);
+      const uint32_t off = (uint32_t)ev * (uint32_t)sizeof(Real);
+      auto ld = [&](int field) -> Real {
+        // the plane base is formed in scalar registers and kept there
+        const char* base = opaque_s((const char*)(planes + (int64_t)field * stride));
+        return *(const Real*)(base + off);
+      };
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        s_[r] = planes[(int64_t)it[r * ITS + 0] * stride + ev];
-        u_[r] = planes[(int64_t)it[r * ITS + 1] * stride + ev];
-        g_[r] = planes[(int64_t)it[r * ITS + 2] * stride + ev];
+        s_[r] = ld(it[r * ITS + 0]);
+        u_[r] = ld(it[r * ITS + 1]);
+        g_[r] = ld(it[r * ITS + 2]);
       }
     }
   };
@@ -443,7 +462,9 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const Real s = sc[r];
-        const Real u = uc[r] * TB(r, TB_UMUL) + TB(r, TB_UADD);
+        // scalar table operands (T == 1): multiply and add, one scalar each
+        const Real u = (T == 1) ? mad_nc(uc[r], TB(r, TB_UMUL), TB(r, TB_UADD))
+                                : uc[r] * TB(r, TB_UMUL) + TB(r, TB_UADD);
         const Real g = gc[r];
         const Real Dr = TB(r, TB_M2) - s;
         const Real Di = TB(r, TB_NGE) * g;
@@ -456,8 +477,10 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
         if constexpr (HVP) {
           // zdot += K1 u w + (K2 + K3 g) u w^2
           const Real uw2r = uwr * wr - uwi * wi, uw2i = uwr * wi + uwi * wr;
-          const Real kr = fma_r(TB(r, TB_K3R), g, TB(r, TB_K2R));
-          const Real ki = fma_r(TB(r, TB_K3I), g, TB(r, TB_K2I));
+          const Real kr = (T == 1) ? mad_nc(TB(r, TB_K3R), g, TB(r, TB_K2R))
+                                   : fma_r(TB(r, TB_K3R), g, TB(r, TB_K2R));
+          const Real ki = (T == 1) ? mad_nc(TB(r, TB_K3I), g, TB(r, TB_K2I))
+                                   : fma_r(TB(r, TB_K3I), g, TB(r, TB_K2I));
           const Real k1r = TB(r, TB_K1R), k1i = TB(r, TB_K1I);
           zdr = fma_r(k1r, uwr, fma_r(-k1i, uwi, fma_r(kr, uw2r, fma_r(-ki, uw2i, zdr))));
           zdi = fma_r(k1r, uwi, fma_r(k1i, uwr, fma_r(kr, uw2i, fma_r(ki, uw2r, zdi))));
@@ -640,15 +663,20 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
   for (int j = 0; j < NA; ++j) acc[j] = 0.0;
 
   if (rg.begin < rg.end) {
+    // Plane loads: wave-uniform plane base + 32-bit byte offset of the event
+    // (the stride is limited to 2^32 bytes per plane at bind time).
+    auto ld = [](const Real* base, uint32_t off) -> Real {
+      return *(const Real*)((const char*)base + off);
+    };
     Real sc[R], uc[R], gc[R];
     {
       const int64_t e = rg.begin + lane;
-      const int64_t ev = rg.base + (e < rg.end ? e : rg.begin);
+      const uint32_t off = (uint32_t)(rg.base + (e < rg.end ? e : rg.begin)) * (uint32_t)sizeof(Real);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        sc[r] = ps[r][ev];
-        uc[r] = pu[r][ev];
-        gc[r] = pg[r][ev];
+        sc[r] = ld(ps[r], off);
+        uc[r] = ld(pu[r], off);
+        gc[r] = ld(pg[r], off);
       }
     }
     int buf = 0;
@@ -657,12 +685,12 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
       Real sn[R], un[R], gn[R];
       {
         const int64_t en = e0 + 64 + lane;
-        const int64_t evn = rg.base + (en < rg.end ? en : rg.begin);
+        const uint32_t off = (uint32_t)(rg.base + (en < rg.end ? en : rg.begin)) * (uint32_t)sizeof(Real);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          sn[r] = ps[r][evn];
-          un[r] = pu[r][evn];
-          gn[r] = pg[r][evn];
+          sn[r] = ld(ps[r], off);
+          un[r] = ld(pu[r], off);
+          gn[r] = ld(pg[r], off);
         }
       }
       CReal* tb = opaque_s((CReal*)tsrc);
@@ -670,22 +698,47 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
       // ---- pass 1: this wave's share of z (and zdot)
       Real cwr[R], cwi[R], cu[R];
       Real zr = 0, zi = 0, zdr = 0, zdi = 0;
+      // D = (M^2 - s) - i Gamma eta g and |D|^2 for the wave's resonances;
+      // in FP64 one reciprocal serves all R (prefix products, then each
+      // 1/|D_r|^2 recovered by multiplications).
+      Real Dr_[R], Di_[R], inv_[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         CReal* t = tb + r * TS;
-        const Real u = uc[r] * t[TB_UMUL] + t[TB_UADD];
+        Dr_[r] = t[TB_M2] - sc[r];
+        Di_[r] = t[TB_NGE] * gc[r];
+        inv_[r] = Dr_[r] * Dr_[r] + Di_[r] * Di_[r];
+      }
+      if constexpr (sizeof(Real) == 8 && R > 1) {
+        Real pre[R];
+        pre[0] = inv_[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r) pre[r] = pre[r - 1] * inv_[r];
+        Real q = rcp_r(pre[R - 1]);
+#pragma unroll
+        for (int r = R - 1; r > 0; --r) {
+          const Real d2 = inv_[r];
+          inv_[r] = q * pre[r - 1];
+          q = q * d2;
+        }
+        inv_[0] = q;
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) inv_[r] = rcp_r(inv_[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        CReal* t = tb + r * TS;
+        const Real u = mad_nc(uc[r], t[TB_UMUL], t[TB_UADD]);
         const Real g = gc[r];
-        const Real Dr = t[TB_M2] - sc[r];
-        const Real Di = t[TB_NGE] * g;
-        const Real inv = rcp_r(Dr * Dr + Di * Di);
-        const Real wr = Dr * inv, wi = -Di * inv;
+        const Real wr = Dr_[r] * inv_[r], wi = -Di_[r] * inv_[r];
         const Real uwr = u * wr, uwi = u * wi;
         zr = fma_r(t[TB_CBR], uwr, fma_r(-t[TB_CBI], uwi, zr));
         zi = fma_r(t[TB_CBR], uwi, fma_r(t[TB_CBI], uwr, zi));
         if constexpr (HVP) {
           const Real uw2r = uwr * wr - uwi * wi, uw2i = uwr * wi + uwi * wr;
-          const Real kr = fma_r(t[TB_K3R], g, t[TB_K2R]);
-          const Real ki = fma_r(t[TB_K3I], g, t[TB_K2I]);
+          const Real kr = mad_nc(t[TB_K3R], g, t[TB_K2R]);
+          const Real ki = mad_nc(t[TB_K3I], g, t[TB_K2I]);
           zdr = fma_r(t[TB_K1R], uwr, fma_r(-t[TB_K1I], uwi, fma_r(kr, uw2r, fma_r(-ki, uw2i, zdr))));
           zdi = fma_r(t[TB_K1R], uwi, fma_r(t[TB_K1I], uwr, fma_r(kr, uw2i, fma_r(ki, uw2r, zdi))));
         }

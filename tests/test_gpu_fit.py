@@ -68,6 +68,6 @@ def test_fit_options(cfg0):
     mask = [0, 0, 1, 1, 1, 1, 1, 1]
     th, rep = lik.fit(th0, xtol=1e-8, free_mask=mask)
     th = th.cpu().numpy()
-    assert rep["converged"] == 1
+    assert rep["converged"] == 1, rep
     np.testing.assert_array_equal(th[:2], th0[:2])
     assert rep["nll"] <= ref.fun + 1e-6
