@@ -49,6 +49,31 @@ def stream_bytes_per_event(n_planes, real_bytes=8):
     return n_planes * real_bytes
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hvp_k12_6M_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2403_09225_amd", "csrc", "pwa_kernels.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (each counter scaled by what it reads for
+    a plain copy of known size), or None when there is no summary for this
+    kernel or the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(TRAFFIC_PROFILE):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel") != kernel or fields.get("source_sha256") != src:
+        return None
+    return (float(fields["fetch_kib_per_dispatch"]) * 1024.0 * float(fields["fetch_calibration"])
+            + float(fields["write_kib_per_dispatch"]) * 1024.0 * float(fields["write_calibration"]))
+
+
 def make_workload():
     """MC: uniform phase space (seeded NumPy).  Data: drawn from the model at
     the generating parameters by accept-reject on the GPU (seeded torch
@@ -88,19 +113,24 @@ def cpu_baseline(W, data, mc, n_data=100_000, n_mc=500_000):
 
 
 def fit_compare(lik, W, cap_s=60.0):
-    """Newton-CG time to minimum from a fixed start: FP64 HVPs vs FP32 HVPs
-    (line search and convergence test in FP64 in both)."""
+    """Newton-CG time to minimum from a fixed start, with FP64 HVPs and with
+    FP32 HVPs inside CG (line search and convergence test in FP64 in both),
+    for scipy's forcing term (the paper's fits) and for the relative one."""
     import synth
     start = W.theta_true + synth.rng_for(1, synth.configs.STREAM_TEST).normal(
         scale=np.tile([0.02, 0.02, 0.002, 0.002], W.n_res))
     out = {}
-    for prec in ("f64", "f32"):
-        th, rep = lik.fit(start, xtol=1e-8, maxiter=200, time_cap_s=cap_s, hvp_precision=prec)
-        out[prec] = {"seconds": round(rep["seconds"], 4), "nll": rep["nll"],
-                     "iterations": rep["iterations"], "hvps": rep["n_hvp"],
-                     "grads": rep["n_grad"], "converged": rep["converged"]}
-    out["speedup_mixed_vs_fp64"] = round(out["f64"]["seconds"] / max(out["f32"]["seconds"], 1e-9), 3)
-    out["nll_diff_mixed_minus_fp64"] = out["f32"]["nll"] - out["f64"]["nll"]
+    for forcing in ("relative", "scipy"):
+        rec = {}
+        for prec in ("f64", "f32"):
+            th, rep = lik.fit(start, xtol=1e-8, maxiter=200, time_cap_s=cap_s, hvp_precision=prec,
+                              forcing=forcing)
+            rec[prec] = {"seconds": round(rep["seconds"], 4), "nll": rep["nll"],
+                         "iterations": rep["iterations"], "hvps": rep["n_hvp"],
+                         "grads": rep["n_grad"], "nlls": rep["n_nll"], "converged": rep["converged"]}
+        rec["speedup_mixed_vs_fp64"] = round(rec["f64"]["seconds"] / max(rec["f32"]["seconds"], 1e-9), 3)
+        rec["nll_diff_mixed_minus_fp64"] = rec["f32"]["nll"] - rec["f64"]["nll"]
+        out[f"forcing_{forcing}"] = rec
     return out
 
 
@@ -250,12 +280,16 @@ def main():
     gbs = bytes_launch / k_avg_s / 1e9
     tfl = flops / k_avg_s / 1e12
     hbm_bound = flops / bytes_launch < FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    traffic = None
+    if args.precision == "f64" and not args.shape:
+        traffic = measured_traffic("wg_kernel<double, 2, 4, 3>")
     roof = {"bound": "hbm" if hbm_bound else "alu",
             "achieved": round(gbs if hbm_bound else tfl, 3),
             "peak": HBM_PEAK_GBS if hbm_bound else FP64_PEAK_TFLOPS,
             "unit": "GB/s" if hbm_bound else "TFLOP/s",
             "frac": round(gbs / HBM_PEAK_GBS if hbm_bound else tfl / FP64_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": "profiles/hvp_k12_6M_hbm_traffic.md" if traffic else None,
             "kernel": f"wg_kernel HVP ({args.precision}), per-event pass",
             "kernel_avg_us": round(k_avg_s * 1e6, 2),
             "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops,

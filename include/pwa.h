@@ -186,9 +186,17 @@ typedef struct pwa_fit_opts {
   int32_t maxiter;        /* outer Newton iterations (<= 0: 200)              */
   int32_t cg_maxiter;     /* CG iterations per Newton step (<= 0: 20 P)        */
   double time_cap_s;      /* wall-clock cap, seconds (<= 0: none); Sec. 3 uses 500 */
-  int32_t hvp_precision;  /* pwa_precision of the HVPs inside CG              */
+  int32_t hvp_precision;  /* pwa_precision of the HVPs inside CG; with
+                             PWA_PREC_F32, Newton steps whose CG forcing term
+                             (see `forcing`) is below 1e-3 use FP64 HVPs
+                             (FP32 ones cannot resolve that tolerance)      */
   int32_t free_mask_set;  /* 0: all parameters free; 1: use free_mask         */
   uint8_t free_mask[4 * PWA_MAX_RES]; /* 1 = free, 0 = fixed                   */
+  int32_t forcing;        /* CG forcing term: 0 = scipy's eta = min(1/2,
+                             sqrt(sum |g|)) (absolute: with many events it
+                             stays 1/2 and Newton-CG converges linearly);
+                             1 = relative eta = min(1/2, sqrt(sum |g| /
+                             sum |g_0|)), superlinear (Eisenstat-Walker)   */
 } pwa_fit_opts;
 
 /* Fit report (host memory, written by pwa_fit). */

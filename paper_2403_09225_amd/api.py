@@ -209,8 +209,10 @@ class Likelihood:
 
     # ------------------------------------------------------------------- fit
     def fit(self, theta0, xtol=1e-8, maxiter=200, cg_maxiter=0, time_cap_s=0.0,
-            hvp_precision="f64", free_mask=None):
-        """Newton-CG fit from theta0; returns (theta, report dict)."""
+            hvp_precision="f64", free_mask=None, forcing="scipy"):
+        """Newton-CG fit from theta0; returns (theta, report dict).
+        forcing: "scipy" (eta = min(1/2, sqrt(sum|g|))) or "relative"
+        (eta = min(1/2, sqrt(sum|g| / sum|g_0|)))."""
         t = self._theta(theta0).clone()
         o = L.PwaFitOpts()
         o.xtol = xtol
@@ -218,6 +220,7 @@ class Likelihood:
         o.cg_maxiter = cg_maxiter
         o.time_cap_s = time_cap_s
         o.hvp_precision = L.PWA_PREC_F32 if hvp_precision == "f32" else L.PWA_PREC_F64
+        o.forcing = {"scipy": 0, "relative": 1}[forcing]
         o.free_mask_set = 0 if free_mask is None else 1
         if free_mask is not None:
             for i, f in enumerate(free_mask):

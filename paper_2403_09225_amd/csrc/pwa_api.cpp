@@ -680,11 +680,15 @@ bool wolfe(Fitter& F, const std::vector<double>& x, double f0, const std::vector
 
 }  // namespace
 
+// Forcing term below which a mixed-precision fit takes its HVPs in FP64.
+constexpr double kMixedEtaSwitch = 1e-3;
+
 int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* rep,
             hipStream_t st) {
   if (!c || !d_theta || !o) return PWA_E_INVALID;
   if (!c->bound) return PWA_E_STATE;
   if (!(o->xtol > 0.0) || !isfinite(o->xtol)) return PWA_E_INVALID;
+  if (o->forcing != 0 && o->forcing != 1) return PWA_E_INVALID;
   const int hp = o->hvp_precision;
   if (check_prec(c, hp) != PWA_OK) return PWA_E_INVALID;
   const auto t0 = std::chrono::steady_clock::now();
@@ -711,7 +715,7 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
   if (hipMemcpyAsync(x.data(), d_theta, sizeof(double) * P, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return PWA_E_HIP;
-  double f;
+  double f, maggrad0 = 1.0;
   int status = PWA_OK, converged = 0, it = 0;
   if (!F.fg(x, f, g)) return F.err;
   if (!isfinite(f)) status = PWA_E_DOMAIN;
@@ -723,8 +727,13 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
     if (o->time_cap_s > 0 && elapsed() > o->time_cap_s) { status = PWA_E_NOCONV; break; }
     // truncated CG on H p = -g (scipy's forcing term and curvature tests)
     const double maggrad = sum_abs(g);
-    const double eta = std::min(0.5, sqrt(maggrad));
+    if (it == 0) maggrad0 = maggrad > 0.0 ? maggrad : 1.0;
+    const double eta = std::min(0.5, sqrt(o->forcing == 1 ? maggrad / maggrad0 : maggrad));
     const double termcond = eta * maggrad;
+    // Mixed precision: FP32 Hessian-vector products carry a relative error
+    // of order 1e-5, so CG cannot meet a tolerance much below that with
+    // them; Newton steps whose forcing term asks for more use FP64 HVPs.
+    F.prec_hvp = (hp == PWA_PREC_F32 && eta < kMixedEtaSwitch) ? PWA_PREC_F64 : hp;
     std::fill(xs.begin(), xs.end(), 0.0);
     r = g;
     for (int i = 0; i < P; ++i) pcg[i] = -g[i];

@@ -45,6 +45,10 @@ __device__ __forceinline__ P* opaque_s(P* p) {
   asm volatile("" : "+s"(p));
   return p;
 }
+__device__ __forceinline__ double sconst(double c) {
+  asm volatile("" : "+s"(c));
+  return c;
+}
 __device__ __forceinline__ int opaque_v(int x) {
   asm volatile("" : "+v"(x));
   return x;
@@ -74,16 +78,18 @@ __device__ __forceinline__ double log_r(double x) {
   e = lo ? e - 1 : e;
   const double y = (m - 1.0) * rcp_r(m + 1.0);
   const double y2 = y * y;
-  double p = 1.0 / 21.0;
-  p = fma(p, y2, 1.0 / 19.0);
-  p = fma(p, y2, 1.0 / 17.0);
-  p = fma(p, y2, 1.0 / 15.0);
-  p = fma(p, y2, 1.0 / 13.0);
-  p = fma(p, y2, 1.0 / 11.0);
-  p = fma(p, y2, 1.0 / 9.0);
-  p = fma(p, y2, 1.0 / 7.0);
-  p = fma(p, y2, 1.0 / 5.0);
-  p = fma(p, y2, 1.0 / 3.0);
+  // the series coefficients are materialised in scalar registers at each
+  // use: hoisted out of the event loop they would occupy vector registers
+  double p = sconst(1.0 / 21.0);
+  p = fma(p, y2, sconst(1.0 / 19.0));
+  p = fma(p, y2, sconst(1.0 / 17.0));
+  p = fma(p, y2, sconst(1.0 / 15.0));
+  p = fma(p, y2, sconst(1.0 / 13.0));
+  p = fma(p, y2, sconst(1.0 / 11.0));
+  p = fma(p, y2, sconst(1.0 / 9.0));
+  p = fma(p, y2, sconst(1.0 / 7.0));
+  p = fma(p, y2, sconst(1.0 / 5.0));
+  p = fma(p, y2, sconst(1.0 / 3.0));
   const double t = 2.0 * y;
   const double r = fma(t * y2, p, t);
   const double de = (double)e;

@@ -35,7 +35,7 @@ from .toys import ToyGenerator
 NBINS = 32
 PAIRS = ((0, 1), (0, 2), (1, 2))     # daughters of channels (12), (13), (23)
 
-# prior of the random starts (and of the toys' true parameters)
+# wide prior: the ranges of the random multi-start of a model-free search
 M_RANGE = (0.6, 1.6)
 G_RANGE = (0.03, 0.3)
 C_RANGE = (0.2, 1.0)
@@ -46,27 +46,65 @@ def threshold(ch, masses=DAUGHTER_MASSES):
     return masses[a] + masses[b]
 
 
+class Prior:
+    """Parameter prior of the toys' true parameters and of the random starts.
+
+    Each resonance has a nominal mass and width (the model hypothesis of an
+    analysis) and a relative spread around them; couplings have |c| uniform
+    in c_range and a uniform phase.  A mass is redrawn while it is below the
+    channel threshold + 20 MeV.  `Prior.wide` spans M in [0.6, 1.6] GeV and
+    Gamma in [0.03, 0.3] GeV for every resonance."""
+
+    def __init__(self, channel, m_nom, g_nom, m_spread, g_spread, c_range=C_RANGE,
+                 masses=DAUGHTER_MASSES):
+        self.channel = list(channel)
+        K = len(self.channel)
+        self.m_nom = np.broadcast_to(np.asarray(m_nom, dtype=np.float64), (K,)).copy()
+        self.g_nom = np.broadcast_to(np.asarray(g_nom, dtype=np.float64), (K,)).copy()
+        self.m_spread = np.broadcast_to(np.asarray(m_spread, dtype=np.float64), (K,)).copy()
+        self.g_spread = np.broadcast_to(np.asarray(g_spread, dtype=np.float64), (K,)).copy()
+        self.c_range = c_range
+        self.thr = np.array([threshold(c, masses) for c in self.channel])
+
+    @classmethod
+    def wide(cls, channel, masses=DAUGHTER_MASSES):
+        mc, gc = 0.5 * sum(M_RANGE), 0.5 * sum(G_RANGE)
+        return cls(channel, mc, gc, 0.5 * (M_RANGE[1] - M_RANGE[0]) / mc,
+                   0.5 * (G_RANGE[1] - G_RANGE[0]) / gc, C_RANGE, masses)
+
+    def draw(self, rng):
+        th = np.empty(4 * len(self.channel))
+        for k in range(len(self.channel)):
+            m = self.m_nom[k] * (1.0 + rng.uniform(-self.m_spread[k], self.m_spread[k]))
+            while m < self.thr[k] + 0.02:
+                m = self.m_nom[k] * (1.0 + rng.uniform(-self.m_spread[k], self.m_spread[k]))
+            g = self.g_nom[k] * (1.0 + rng.uniform(-self.g_spread[k], self.g_spread[k]))
+            mag, ph = rng.uniform(*self.c_range), rng.uniform(0.0, 2.0 * np.pi)
+            th[4 * k:4 * k + 4] = (mag * np.cos(ph), mag * np.sin(ph), m, g)
+        return th
+
+    def code(self, m, g):
+        return (m / self.m_nom - 1.0) / self.m_spread, (g / self.g_nom - 1.0) / self.g_spread
+
+    def uncode(self, ym, yg):
+        return self.m_nom * (1.0 + self.m_spread * ym), self.g_nom * (1.0 + self.g_spread * yg)
+
+
 def draw_start(channel, rng, masses=DAUGHTER_MASSES):
-    """Random parameters from the prior: M ~ U(M_RANGE) above the channel
-    threshold + 20 MeV, Gamma ~ U(G_RANGE), |c| ~ U(C_RANGE), uniform phase."""
-    th = np.empty(4 * len(channel))
-    for k, ch in enumerate(channel):
-        m = rng.uniform(*M_RANGE)
-        while m < threshold(ch, masses) + 0.02:
-            m = rng.uniform(*M_RANGE)
-        g = rng.uniform(*G_RANGE)
-        mag, ph = rng.uniform(*C_RANGE), rng.uniform(0.0, 2.0 * np.pi)
-        th[4 * k:4 * k + 4] = (mag * np.cos(ph), mag * np.sin(ph), m, g)
-    return th
+    """A random start from the wide prior."""
+    return Prior.wide(channel, masses).draw(rng)
 
 
 class StartCoder:
-    """Canonical form and the affine coding of parameter vectors."""
+    """Canonical form and the affine coding of parameter vectors: couplings
+    rotated and scaled as described above, M and Gamma by the prior's
+    nominal values and spreads (the prior's range maps onto [-1, 1])."""
 
-    def __init__(self, channel, spin, masses=DAUGHTER_MASSES):
+    def __init__(self, channel, spin, prior=None, masses=DAUGHTER_MASSES):
         self.channel, self.spin = list(channel), list(spin)
         self.K = len(channel)
         self.P = 4 * self.K
+        self.prior = prior if prior is not None else Prior.wide(channel, masses)
         groups = {}
         for k, key in enumerate(zip(channel, spin)):
             groups.setdefault(key, []).append(k)
@@ -76,8 +114,11 @@ class StartCoder:
     def canonical(self, theta):
         th = np.asarray(theta, dtype=np.float64).reshape(self.K, 4).copy()
         for g in self.groups:
-            order = sorted(g, key=lambda k: th[k, 2])
-            th[g] = th[order]
+            # interchangeable resonances: the k-th lightest takes the slot of
+            # the k-th lightest nominal mass (by mass alone for equal nominals)
+            by_mass = sorted(g, key=lambda k: th[k, 2])
+            slots = sorted(g, key=lambda k: self.prior.m_nom[k])
+            th[slots] = th[by_mass]
         c = th[:, 0] + 1j * th[:, 1]
         if abs(c[0]) > 0:
             c = c * np.exp(-1j * np.angle(c[0]))
@@ -90,20 +131,17 @@ class StartCoder:
     def encode(self, theta):
         th = self.canonical(theta).reshape(self.K, 4)
         y = th.copy()
-        y[:, 2] = (th[:, 2] - 0.5 * sum(M_RANGE)) / (0.5 * (M_RANGE[1] - M_RANGE[0]))
-        y[:, 3] = (th[:, 3] - 0.5 * sum(G_RANGE)) / (0.5 * (G_RANGE[1] - G_RANGE[0]))
+        y[:, 2], y[:, 3] = self.prior.code(th[:, 2], th[:, 3])
         return y.reshape(-1)
 
     def decode(self, y):
         y = np.asarray(y, dtype=np.float64).reshape(self.K, 4)
         th = y.copy()
-        th[:, 2] = 0.5 * sum(M_RANGE) + 0.5 * (M_RANGE[1] - M_RANGE[0]) * y[:, 2]
-        th[:, 3] = 0.5 * sum(G_RANGE) + 0.5 * (G_RANGE[1] - G_RANGE[0]) * y[:, 3]
+        th[:, 2], th[:, 3] = self.prior.uncode(y[:, 2], y[:, 3])
         th[:, 2] = np.maximum(th[:, 2], self.thr + 0.02)
-        th[:, 3] = np.clip(th[:, 3], 0.5 * G_RANGE[0], 2.0 * G_RANGE[1])
+        th[:, 3] = np.maximum(th[:, 3], 0.25 * self.prior.g_nom * (1.0 - self.prior.g_spread) + 1e-3)
         c = th[:, 0] + 1j * th[:, 1]
-        if not np.all(np.abs(c) > 1e-3):     # keep every coupling alive
-            c = np.where(np.abs(c) > 1e-3, c, 1e-3)
+        c = np.where(np.abs(c) > 1e-3, c, 1e-3)    # keep every coupling alive
         th[:, 0], th[:, 1] = c.real, c.imag
         return th.reshape(-1)
 
@@ -239,16 +277,18 @@ class MLP:
 # Toy fits: training data and evaluation.
 # ---------------------------------------------------------------------------
 def fit(lik, start, xtol=1e-6, maxiter=100, time_cap_s=5.0):
-    th, rep = lik.fit(start, xtol=xtol, maxiter=maxiter, time_cap_s=time_cap_s)
+    th, rep = lik.fit(start, xtol=xtol, maxiter=maxiter, time_cap_s=time_cap_s,
+                      forcing="relative")
     return th.cpu().numpy(), rep
 
 
 class ToyStudy:
     """Toys of one resonance layout with a shared MC sample."""
 
-    def __init__(self, channel, spin, n_mc, seed=0, device="cuda"):
+    def __init__(self, channel, spin, n_mc, prior=None, seed=0, device="cuda"):
         self.channel, self.spin = list(channel), list(spin)
-        self.coder = StartCoder(channel, spin)
+        self.prior = prior if prior is not None else Prior.wide(channel)
+        self.coder = StartCoder(channel, spin, self.prior)
         self.gen = torch.Generator(device=device)
         self.gen.manual_seed(seed)
         self.rng = np.random.Generator(np.random.PCG64(seed))
@@ -259,7 +299,7 @@ class ToyStudy:
 
     def toy(self, n_events):
         """(true canonical theta, events) of one toy."""
-        th = self.coder.canonical(draw_start(self.channel, self.rng))
+        th = self.coder.canonical(self.prior.draw(self.rng))
         ev = self.toys.draw(th, n_events, self.gen)
         return th, ev
 
@@ -333,7 +373,7 @@ class ToyStudy:
             lik = self.likelihood(ev)
             start = self.propose(net, self.features(ev, n_events))[0]
             fits = {"truth": fit(lik, th), "proposal": fit(lik, start)}
-            rnd = [fit(lik, draw_start(self.channel, self.rng)) for _ in range(n_random)]
+            rnd = [fit(lik, self.prior.draw(self.rng)) for _ in range(n_random)]
             nlls = [f[1]["nll"] for f in list(fits.values()) + rnd]
             nmin = min(x for x in nlls if np.isfinite(x))
             ok = lambda rep: np.isfinite(rep["nll"]) and rep["nll"] <= nmin + tol  # noqa: E731
@@ -394,12 +434,22 @@ def main(argv=None):
     ap.add_argument("--eval-events", type=int, default=100000)
     ap.add_argument("--random", type=int, default=32, help="random starts per held-out toy")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--m-spread", type=float, default=0.03,
+                    help="relative mass spread around the nominal masses (0: wide prior)")
+    ap.add_argument("--g-spread", type=float, default=0.2, help="relative width spread")
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
     ch, sp = resonance_layout(a.K)
+    if a.m_spread > 0:
+        # the analysis model: nominal masses and widths drawn once from the wide prior
+        nom = Prior.wide(ch).draw(np.random.Generator(np.random.PCG64(a.seed + 7)))
+        prior = Prior(ch, nom[2::4], nom[3::4], a.m_spread, a.g_spread)
+    else:
+        prior = Prior.wide(ch)
     t0 = time.time()
-    study = ToyStudy(ch, sp, a.mc, seed=a.seed)
-    x, y, ids = study.training_set(a.train, a.events, log_every=max(1, a.train // 10), n_rep=a.rep)
+    study = ToyStudy(ch, sp, a.mc, prior=prior, seed=a.seed)
+    x, y, ids = study.training_set(a.train, a.events, log_every=max(1, min(50, a.train // 10)),
+                                   n_rep=a.rep)
     t_data = time.time() - t0
     toys = np.unique(ids)
     n_val = int(round(a.val * len(toys)))
@@ -421,9 +471,9 @@ def main(argv=None):
     print(f"[learned-start] trained: loss {losses[0]:.4f} -> {losses[-1]:.4f}; validation "
           f"{vh[0] if vh else float('nan'):.4f} -> best {min(vh) if vh else float('nan'):.4f} "
           f"(epoch {int(np.argmin(vh)) + 1 if vh else 0})", flush=True)
-    ev = ToyStudy(ch, sp, a.mc, seed=a.seed + 1000)
-    summary, _ = ev.evaluate(net, a.eval, a.eval_events, a.random, log_every=max(1, a.eval // 10))
-    summary.update({"K": a.K, "train_toys": int(len(toys) - n_val), "val_toys": n_val,
+    ev = ToyStudy(ch, sp, a.mc, prior=prior, seed=a.seed + 1000)
+    summary, _ = ev.evaluate(net, a.eval, a.eval_events, a.random, log_every=max(1, min(5, a.eval // 10)))
+    summary.update({"K": a.K, "m_spread": a.m_spread, "g_spread": a.g_spread, "train_toys": int(len(toys) - n_val), "val_toys": n_val,
                     "train_rows": int(x.shape[0]), "train_events": a.events, "mc": a.mc,
                     "epochs": a.epochs, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
                     "val_loss_best": min(vh) if vh else None,
