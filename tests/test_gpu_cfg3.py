@@ -1,0 +1,125 @@
+"""Differentiation at scale: K = 30 resonances (120 parameters) over 4M data
+and 20M MC events, FP64 and FP32 event streams.
+
+* gradient and H v against the oracle on a 50k + 250k subsample (the FP64
+  tolerance rule of the parity tests: 1e-10 of each component's
+  absolute-sum scale);
+* over all 24M events: the GPU FP64 NLL's central difference (Richardson,
+  h = 1e-6 and 5e-7) along a random direction equals g . d, and the central
+  difference of GPU gradients equals H d;
+* the FP32 stream (FP64 reductions) tracks the FP64 stream: NLL to 1e-5
+  relative, gradient and H v to 1e-3 of their largest component;
+* the autograd wrapper's double backward returns pwa_hvp's H v;
+* memory: the workspace grows by the event stream only (18 planes), nothing
+  is stored per event for the derivatives.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_cases import Model, assert_close, likelihood, oracle_all
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    W = synth.workload(3)
+    say(f"[cfg3] generating {W.n_data} + {W.n_mc} events, K = {W.n_res}")
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(3, synth.configs.STREAM_MC))
+    data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
+                               synth.rng_for(3, synth.configs.STREAM_DATA))
+    lik = likelihood(W, data, mc, streams=("f64", "f32"))
+    return W, data, mc, lik
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def test_cfg3_subsample_against_oracle(cfg3):
+    W, data, mc, _ = cfg3
+    say("[cfg3] 50k + 250k subsample vs oracle")
+    d = (data[0][:50_000], data[1][:50_000])
+    m = (mc[0][:250_000], mc[1][:250_000])
+    model = Model(W.channel, W.spin)
+    v = synth.rng_for(3, synth.configs.STREAM_TEST).normal(size=W.n_par)
+    f, g, hv, S, SH = oracle_all(model, d, m, W.theta_true, v)
+    lik = likelihood(model, d, m)
+    hv_g, f_g, g_g = lik.hvp(W.theta_true, v)
+    assert abs(float(f_g) - f) <= 1e-10 * abs(f)
+    assert_close("grad", _np(g_g), g, S, 1e-10)
+    assert_close("hvp", _np(hv_g), hv, SH, 1e-10)
+
+
+def test_cfg3_central_differences(cfg3):
+    W, data, mc, lik = cfg3
+    say("[cfg3] central differences over 24M events")
+    th = W.theta_true
+    d = synth.rng_for(3, 6).normal(size=W.n_par)
+    hv, _, g = lik.hvp(th, d)
+    g, hv = _np(g), _np(hv)
+
+    def fcd(h):
+        return (float(lik.nll(th + h * d)) - float(lik.nll(th - h * d))) / (2 * h)
+
+    def gcd(h):
+        return (_np(lik.grad(th + h * d)[1]) - _np(lik.grad(th - h * d)[1])) / (2 * h)
+
+    h = 1e-6
+    fd = (4.0 * fcd(h / 2) - fcd(h)) / 3.0
+    assert abs(fd - g @ d) <= 1e-5 * np.abs(g).max() * np.abs(d).sum()
+    hfd = (4.0 * gcd(h / 2) - gcd(h)) / 3.0
+    assert np.max(np.abs(hfd - hv)) <= 1e-5 * np.max(np.abs(hv))
+
+
+def test_cfg3_fp32_stream_tracks_fp64(cfg3):
+    W, data, mc, lik = cfg3
+    say("[cfg3] FP32 stream vs FP64 stream")
+    th = W.theta_true
+    v = synth.rng_for(3, 7).normal(size=W.n_par)
+    hv64, f64, g64 = [_np(x) for x in lik.hvp(th, v)]
+    lik.set_precision("f32")
+    try:
+        hv32, f32, g32 = [_np(x) for x in lik.hvp(th, v)]
+    finally:
+        lik.set_precision("f64")
+    assert abs(float(f32) - float(f64)) <= 1e-5 * abs(float(f64))
+    assert np.max(np.abs(g32 - g64)) <= 1e-3 * np.max(np.abs(g64))
+    assert np.max(np.abs(hv32 - hv64)) <= 1e-3 * np.max(np.abs(hv64))
+
+
+def test_cfg3_autograd_double_backward(cfg3):
+    W, data, mc, lik = cfg3
+    say("[cfg3] autograd double backward")
+    from paper_2403_09225_amd import nll as nll_fn
+    th = torch.tensor(W.theta_true, dtype=torch.float64, device="cuda", requires_grad=True)
+    v = torch.tensor(synth.rng_for(3, 8).normal(size=W.n_par), dtype=torch.float64, device="cuda")
+    f = nll_fn(th, lik)
+    (g,) = torch.autograd.grad(f, th, create_graph=True)
+    (hv,) = torch.autograd.grad(g, th, grad_outputs=v)
+    hv_ref, f_ref, g_ref = lik.hvp(W.theta_true, v)
+    # NLL and gradient come from the NLL and gradient passes (their own
+    # summation order); the double backward is pwa_hvp itself
+    assert float(f.detach()) == pytest.approx(float(f_ref), rel=1e-13)
+    gs = float(torch.max(torch.abs(g_ref)))
+    assert float(torch.max(torch.abs(g.detach() - g_ref))) <= 1e-11 * gs
+    assert torch.equal(hv, hv_ref)
+
+
+def test_cfg3_memory_is_the_event_stream(cfg3):
+    W, _, _, lik = cfg3
+    n = W.n_data + W.n_mc
+    grow = lik.workspace_bytes(W.n_data, W.n_mc) - lik.workspace_bytes(0, 1)
+    stream = 18 * (8 + 4) * n          # FP64 and FP32 planes
+    # planes are padded to a multiple of 64 events and regions to 256 bytes
+    assert abs(grow - stream) <= 18 * 12 * 64 + 4096
