@@ -23,6 +23,7 @@ onto [-1, 1].
 """
 
 import ctypes
+import os
 import time
 
 import numpy as np
@@ -192,6 +193,25 @@ class MLP:
         self._ws, self._ws_batch = None, 0
         self.cast()
 
+    def save(self, path, **meta):
+        """FP32 master weights, the layer widths and `meta` (numbers, arrays
+        or strings) to an .npz file."""
+        np.savez_compressed(path, w=self.w.cpu().numpy(),
+                            dims=np.array([self.n_in, self.n_h1, self.n_h2, self.n_out]),
+                            **{k: np.asarray(v) for k, v in meta.items()})
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        """(network, meta dict) from a file written by save."""
+        d = np.load(path, allow_pickle=False)
+        net = cls(tuple(int(x) for x in d["dims"]), device=device)
+        w = torch.as_tensor(d["w"], dtype=torch.float32, device=net.device)
+        if w.numel() != net.n_params:
+            raise ValueError("weight file does not match the layer widths")
+        net.w.copy_(w)
+        net.cast()
+        return net, {k: d[k] for k in d.files if k not in ("w", "dims")}
+
     def cast(self):
         L.check("pwa_mlp_cast", self.lib.pwa_mlp_cast(ctypes.byref(self.dims), _ptr(self.w),
                                                       _ptr(self.wbf), _ptr(self.wtbf), _stream()))
@@ -307,10 +327,17 @@ class ToyStudy:
         lik = Likelihood(self.channel, self.spin, device=self.device)
         return lik.bind(ev[0], ev[1], self.mc[0], self.mc[1])
 
+    @staticmethod
+    def transform(h):
+        """Network input from normalised histograms: the square root of the
+        density scaled by the bin count (a flat distribution over the box
+        gives 1 per bin; the square root evens out the Poisson noise of the
+        bins)."""
+        return torch.sqrt(h * float(NBINS * NBINS))
+
     def features(self, ev, n_events):
-        """Network input of one event set: its histogram scaled by the bin
-        count (a flat distribution over the box gives 1 per bin)."""
-        return histograms(ev[0], ev[1], [0, n_events]) * float(NBINS * NBINS)
+        """Network input of one event set."""
+        return self.transform(histograms(ev[0], ev[1], [0, n_events]))
 
     def resampled_features(self, ev, n_events, n_rep):
         """Features of n_rep bootstrap resamples of one event set (the
@@ -318,13 +345,14 @@ class ToyStudy:
         idx = torch.randint(0, n_events, (n_rep * n_events,), generator=self.gen,
                             device=ev[0].device)
         off = torch.arange(0, n_rep + 1, dtype=torch.int64, device=ev[0].device) * n_events
-        return histograms(ev[0][idx], ev[1][idx], off) * float(NBINS * NBINS)
+        return self.transform(histograms(ev[0][idx], ev[1][idx], off))
 
     def training_set(self, n_toys, n_events, log_every=0, label_bound=4.0, n_rep=0):
-        """Features and coded labels of toy fits started at the truth.  Fits
-        that do not converge, or end with a coded parameter beyond
-        +-label_bound (a resonance the toy does not constrain wandering off),
-        are left out.  With n_rep > 0, each toy also contributes n_rep
+        """Features and coded labels of toy fits started at the truth (the
+        fit's best point, also when it stops before meeting xtol).  A coded
+        mass or width beyond +-label_bound (a resonance the toy does not
+        constrain wandering off) is clipped to it; a fit whose couplings end
+        beyond it is left out.  With n_rep > 0, each toy also contributes n_rep
         bootstrap resamples of its events with the same label; the toy index
         of every row is returned so that a validation split can keep whole
         toys apart."""
@@ -334,11 +362,13 @@ class ToyStudy:
             th, ev = self.toy(n_events)
             lik = self.likelihood(ev)
             th_fit, rep = fit(lik, th)
-            if not np.all(np.isfinite(th_fit)) or not rep["converged"]:
+            if not np.all(np.isfinite(th_fit)) or not np.isfinite(rep["nll"]):
                 continue
-            y = self.coder.encode(th_fit)
-            if np.max(np.abs(y)) > label_bound:
+            y = self.coder.encode(th_fit).reshape(-1, 4)
+            if np.max(np.abs(y[:, :2])) > label_bound:
                 continue
+            y[:, 2:] = np.clip(y[:, 2:], -label_bound, label_bound)
+            y = y.reshape(-1)
             f = self.features(ev, n_events)
             if n_rep:
                 f = torch.cat([f, self.resampled_features(ev, n_events, n_rep)])
@@ -356,16 +386,18 @@ class ToyStudy:
         y = net.forward(hists).cpu().numpy().astype(np.float64)
         return [self.coder.decode(r) for r in y]
 
-    def evaluate(self, net, n_toys, n_events, n_random, tol=0.01, log_every=0):
+    def evaluate(self, net, n_toys, n_events, n_random, tol=0.01, log_every=0, blind=None):
         """Proposal-started fits against random multi-start on held-out toys.
 
         Per toy, NLL_min is the lowest NLL of all its fits (from the truth,
-        the proposal and every random start); a fit succeeds when its NLL is
-        within `tol` of it.  Random multi-start is priced as the expected
-        cost until its first success over a random order of its starts
-        (failures before the first success count in full); the proposal
-        strategy costs its own fit plus, when that fails, the random
-        strategy's expected cost."""
+        the proposal, the blind start and every random start); a fit
+        succeeds when its NLL is within `tol` of it.  Random multi-start is
+        priced as the expected cost until its first success over a random
+        order of its starts (failures before the first success count in
+        full); a single-start strategy (the proposal, or the blind start
+        `blind` -- one fixed start that ignores the data, e.g. the decoded
+        mean training label) costs its own fit plus, when that fails, the
+        random strategy's expected cost."""
         rows = []
         t0 = time.time()
         for i in range(n_toys):
@@ -373,6 +405,8 @@ class ToyStudy:
             lik = self.likelihood(ev)
             start = self.propose(net, self.features(ev, n_events))[0]
             fits = {"truth": fit(lik, th), "proposal": fit(lik, start)}
+            if blind is not None:
+                fits["blind"] = fit(lik, blind)
             rnd = [fit(lik, self.prior.draw(self.rng)) for _ in range(n_random)]
             nlls = [f[1]["nll"] for f in list(fits.values()) + rnd]
             nmin = min(x for x in nlls if np.isfinite(x))
@@ -388,27 +422,49 @@ class ToyStudy:
                 good = sum(c for c, s in zip(costs, succ) if s)
                 return fail / (S + 1) + good / S, True
 
-            p_ok = ok(fits["proposal"][1])
-            row = {"proposal_success": bool(p_ok), "random_success_fraction": S / max(1, n_random)}
-            for key in ("iterations", "seconds"):
-                e_rnd, found = expected(key)
-                row[f"random_{key}"] = e_rnd
-                row["random_found"] = found
-                row[f"proposal_{key}"] = fits["proposal"][1][key] + (0.0 if p_ok else e_rnd)
+            row = {"random_success_fraction": S / max(1, n_random)}
+            for name in ("proposal", "blind"):
+                if name not in fits:
+                    continue
+                s_ok = ok(fits[name][1])
+                row[f"{name}_success"] = bool(s_ok)
+                for key in ("iterations", "seconds"):
+                    e_rnd, found = expected(key)
+                    row[f"random_{key}"] = e_rnd
+                    row["random_found"] = found
+                    row[f"{name}_{key}"] = fits[name][1][key] + (0.0 if s_ok else e_rnd)
             rows.append(row)
             if log_every and (i + 1) % log_every == 0:
                 print(f"[learned-start] evaluated {i + 1}/{n_toys} toys, {time.time() - t0:.1f} s",
                       flush=True)
         summary = {
             "toys": n_toys, "events_per_toy": n_events, "random_starts": n_random, "tol": tol,
-            "proposal_success_rate": float(np.mean([r["proposal_success"] for r in rows])),
             "random_start_success_rate": float(np.mean([r["random_success_fraction"] for r in rows])),
-            "mean_iterations_proposal_strategy": float(np.mean([r["proposal_iterations"] for r in rows])),
+            "random_found_fraction": float(np.mean([r["random_found"] for r in rows])),
             "mean_iterations_random_strategy": float(np.mean([r["random_iterations"] for r in rows])),
-            "mean_seconds_proposal_strategy": float(np.mean([r["proposal_seconds"] for r in rows])),
             "mean_seconds_random_strategy": float(np.mean([r["random_seconds"] for r in rows])),
         }
+        for name in ("proposal", "blind"):
+            if f"{name}_success" in rows[0]:
+                summary[f"{name}_success_rate"] = float(np.mean([r[f"{name}_success"] for r in rows]))
+                summary[f"mean_iterations_{name}_strategy"] = float(np.mean([r[f"{name}_iterations"] for r in rows]))
+                summary[f"mean_seconds_{name}_strategy"] = float(np.mean([r[f"{name}_seconds"] for r in rows]))
         return summary, rows
+
+
+DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+
+
+def load_proposal(path=None, device="cuda"):
+    """A trained start proposal: (network, prior, blind start, metadata).
+    The default is the K = 12 network shipped in data/ (trained by this
+    module's main() on 4500 toy fits; see its metadata)."""
+    net, meta = MLP.load(path or os.path.join(DATA, "start_proposal_k12.npz"), device=device)
+    K = int(meta["K"])
+    ch, _ = resonance_layout(K)
+    prior = Prior(ch, meta["m_nom"], meta["g_nom"], meta["m_spread"], meta["g_spread"],
+                  tuple(float(c) for c in meta["c_range"]))
+    return net, prior, np.asarray(meta["blind"], dtype=np.float64), meta
 
 
 def resonance_layout(K):
@@ -427,7 +483,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--rep", type=int, default=4, help="bootstrap resamples per training toy")
-    ap.add_argument("--wd", type=float, default=1e-4, help="decoupled weight decay")
+    ap.add_argument("--wd", default="1e-4", help="decoupled weight decay; a comma-separated "
+                    "list trains one network per value and keeps the lowest validation loss")
     ap.add_argument("--val", type=float, default=0.1, help="fraction of toys held for validation")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval", type=int, default=40, help="held-out toys")
@@ -438,6 +495,10 @@ def main(argv=None):
                     help="relative mass spread around the nominal masses (0: wide prior)")
     ap.add_argument("--g-spread", type=float, default=0.2, help="relative width spread")
     ap.add_argument("--out", default="")
+    ap.add_argument("--save-net", default="", help="save the trained network and its prior "
+                    "to this .npz")
+    ap.add_argument("--save-set", default="", help="save the training features (one row per "
+                    "toy, float16) and labels to this .npz")
     a = ap.parse_args(argv)
     ch, sp = resonance_layout(a.K)
     if a.m_spread > 0:
@@ -451,29 +512,46 @@ def main(argv=None):
     x, y, ids = study.training_set(a.train, a.events, log_every=max(1, min(50, a.train // 10)),
                                    n_rep=a.rep)
     t_data = time.time() - t0
+    if a.save_set:
+        first = np.concatenate([[True], ids[1:] != ids[:-1]])
+        np.savez_compressed(a.save_set, x=x[torch.as_tensor(first, device=x.device)].cpu().numpy().astype(np.float16),
+                            y=y[torch.as_tensor(first, device=y.device)].cpu().numpy(), toy=ids[first])
     toys = np.unique(ids)
     n_val = int(round(a.val * len(toys)))
     val_toys = set(np.random.Generator(np.random.PCG64(a.seed)).choice(toys, n_val, replace=False))
     is_val = torch.as_tensor([i in val_toys for i in ids], device=x.device)
     xv, yv = x[is_val], y[is_val]
     x, y = x[~is_val], y[~is_val]
-    net = MLP((NBINS * NBINS, 512, 512, 4 * a.K), seed=a.seed)
-    t1 = time.time()
     yc = y.cpu().numpy()
     print(f"[learned-start] {x.shape[0]} labels: mean |y| {np.mean(np.abs(yc)):.3f}, "
           f"std {yc.std():.3f}, max |y| {np.max(np.abs(yc)):.3f}", flush=True)
-    losses = net.train(x, y, epochs=a.epochs, batch=min(a.batch, int(x.shape[0])), lr=a.lr,
-                       lr_end=a.lr * 0.05, seed=a.seed, weight_decay=a.wd,
-                       x_val=xv if n_val else None, t_val=yv if n_val else None)
+    t1 = time.time()
+    best = None
+    for wd in [float(w) for w in str(a.wd).split(",")]:
+        cand = MLP((NBINS * NBINS, 512, 512, 4 * a.K), seed=a.seed)
+        losses = cand.train(x, y, epochs=a.epochs, batch=min(a.batch, int(x.shape[0])), lr=a.lr,
+                            lr_end=a.lr * 0.05, seed=a.seed, weight_decay=wd,
+                            x_val=xv if n_val else None, t_val=yv if n_val else None)
+        vh = cand.val_history
+        vbest = min(vh) if vh else float("nan")
+        print(f"[learned-start] weight decay {wd:g}: loss {losses[0]:.4f} -> {losses[-1]:.4f}; "
+              f"validation {vh[0] if vh else float('nan'):.4f} -> best {vbest:.4f} "
+              f"(epoch {int(np.argmin(vh)) + 1 if vh else 0})", flush=True)
+        if best is None or (vh and vbest < best[0]):
+            best = (vbest, wd, cand, losses, vh)
+    _, wd_best, net, losses, vh = best
     torch.cuda.synchronize()
     t_train = time.time() - t1
-    vh = net.val_history
-    print(f"[learned-start] trained: loss {losses[0]:.4f} -> {losses[-1]:.4f}; validation "
-          f"{vh[0] if vh else float('nan'):.4f} -> best {min(vh) if vh else float('nan'):.4f} "
-          f"(epoch {int(np.argmin(vh)) + 1 if vh else 0})", flush=True)
+    blind = study.coder.decode(y.mean(0).cpu().numpy().astype(np.float64))
+    if a.save_net:
+        net.save(a.save_net, K=a.K, blind=blind, m_nom=prior.m_nom, g_nom=prior.g_nom, m_spread=prior.m_spread,
+                 g_spread=prior.g_spread, c_range=np.asarray(prior.c_range),
+                 train_toys=int(len(toys) - n_val), train_events=a.events, mc=a.mc,
+                 val_loss_best=min(vh) if vh else np.nan, seed=a.seed)
     ev = ToyStudy(ch, sp, a.mc, prior=prior, seed=a.seed + 1000)
-    summary, _ = ev.evaluate(net, a.eval, a.eval_events, a.random, log_every=max(1, min(5, a.eval // 10)))
-    summary.update({"K": a.K, "m_spread": a.m_spread, "g_spread": a.g_spread, "train_toys": int(len(toys) - n_val), "val_toys": n_val,
+    summary, _ = ev.evaluate(net, a.eval, a.eval_events, a.random, log_every=max(1, min(5, a.eval // 10)),
+                             blind=blind)
+    summary.update({"K": a.K, "m_spread": a.m_spread, "g_spread": a.g_spread, "weight_decay": wd_best, "train_toys": int(len(toys) - n_val), "val_toys": n_val,
                     "train_rows": int(x.shape[0]), "train_events": a.events, "mc": a.mc,
                     "epochs": a.epochs, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
                     "val_loss_best": min(vh) if vh else None,
