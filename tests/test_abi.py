@@ -184,3 +184,19 @@ def test_mlp_host_validation(lib):
     masses = (ctypes.c_double * 3)(0.494, 0.140, 0.140)
     assert lib.pwa_hist2d(fake, fake, fake, 0, 1.865, masses, fake, st) == L.PWA_E_INVALID
     assert lib.pwa_hist2d(fake, fake, fake, 1, 0.5, masses, fake, st) == L.PWA_E_INVALID
+
+
+def test_event_count_limit(lib):
+    """Planes are addressed with 32-bit byte offsets: at most 2^29 - 64 events
+    per context (FP64); beyond that the workspace query returns 0 and bind
+    rejects the sizes before any device call."""
+    code, h = _create(lib, _model())
+    assert code == L.PWA_OK
+    try:
+        lim = (1 << 29) - 64
+        assert lib.pwa_workspace_bytes(h, lim - 10, 10) > 0
+        assert lib.pwa_workspace_bytes(h, lim - 9, 10) == 0
+        fake = ctypes.c_void_p(0x1000)
+        assert lib.pwa_bind(h, fake, fake, lim, fake, fake, 10, fake, 1 << 40, None) == L.PWA_E_INVALID
+    finally:
+        lib.pwa_destroy(h)
