@@ -650,7 +650,10 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
   const int64_t stride = a.stride;
   const Real* tsrc = ((sizeof(Real) == 8) ? (const Real*)a.tbl64 : (const Real*)a.tbl32) + wv * R * TS;
 
-  __shared__ Real xch[2][G][64][NX];
+  // z and zdot exchange, double buffered: one array of (re, im) pairs per
+  // quantity, so each lane's access is one contiguous pair (a 32-byte
+  // per-lane stride for FP64 would conflict in the LDS banks)
+  __shared__ Real xch[2][G][NX / 2][64][2];
 
   const Real* ps[R];
   const Real* pu[R];
@@ -754,21 +757,21 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
       }
       // ---- exchange: every wave sums the G shares in group order
       if constexpr (G > 1) {
-        xch[buf][wv][lane][0] = zr;
-        xch[buf][wv][lane][1] = zi;
+        xch[buf][wv][0][lane][0] = zr;
+        xch[buf][wv][0][lane][1] = zi;
         if constexpr (HVP) {
-          xch[buf][wv][lane][2] = zdr;
-          xch[buf][wv][lane][3] = zdi;
+          xch[buf][wv][1][lane][0] = zdr;
+          xch[buf][wv][1][lane][1] = zdi;
         }
         __syncthreads();
         zr = zi = zdr = zdi = 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          zr += xch[buf][g][lane][0];
-          zi += xch[buf][g][lane][1];
+          zr += xch[buf][g][0][lane][0];
+          zi += xch[buf][g][0][lane][1];
           if constexpr (HVP) {
-            zdr += xch[buf][g][lane][2];
-            zdi += xch[buf][g][lane][3];
+            zdr += xch[buf][g][1][lane][0];
+            zdi += xch[buf][g][1][lane][1];
           }
         }
       }
