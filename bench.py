@@ -112,6 +112,47 @@ def cpu_baseline(W, data, mc, n_data=100_000, n_mc=500_000):
             "host_cores_available": len(os.sched_getaffinity(0))}
 
 
+def _oracle_shard(args):
+    import oracle
+    d, m, W, theta, v = args
+    return oracle.partials(d, m, W, theta, v=v)
+
+
+def cpu_all_cores(W, data, mc, n_data=200_000, n_mc=1_000_000):
+    """The oracle on all host cores: a process pool over contiguous event
+    shards, combined by eq. (4)-(7) (the oracle's own combine); the same 1:5
+    data:MC mix as the workload, one NLL+grad+HVP."""
+    import multiprocessing as mp
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    v = np.random.Generator(np.random.PCG64(5)).normal(size=W.n_par)
+    nd, nm = n_data // cores, n_mc // cores
+    jobs = [((data[0][i * nd:(i + 1) * nd], data[1][i * nd:(i + 1) * nd]),
+             (mc[0][i * nm:(i + 1) * nm], mc[1][i * nm:(i + 1) * nm]), W, W.theta_true, v)
+            for i in range(cores)]
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    try:
+        # fresh interpreters: the workers never inherit this process's GPU state
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        with ctx.Pool(cores) as pool:
+            parts = pool.map(_oracle_shard, jobs)
+        oracle.combine(parts, v=v)
+        dt = time.perf_counter() - t0
+    finally:
+        for k, val in env.items():
+            if val is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = val
+    n = cores * (nd + nm)
+    return {"value": n / dt, "unit": "events/s", "cores": cores, "kind": "oracle",
+            "sample": f"one NLL+grad+HVP of the oracle over {cores * nd} data + {cores * nm} MC events "
+                      f"in {cores} processes (eq. (4)-(7) combine); {dt:.2f} s"}
+
+
 def fit_compare(lik, W, cap_s=60.0):
     """Newton-CG time to minimum from a fixed start, with FP64 HVPs and with
     FP32 HVPs inside CG (line search and convergence test in FP64 in both),
@@ -304,7 +345,10 @@ def main():
                                "1M events drawn from the model + 5M uniform MC events; "
                                "one fused NLL+grad+HVP pass (Newton-CG inner step)",
                    "n_res": W.n_res, "n_data": W.n_data, "n_mc": W.n_mc,
-                   "launch_shape": args.shape or "auto", "grid_blocks": lik.grid_blocks()},
+                   "launch_shape": args.shape or "auto", "grid_blocks": lik.grid_blocks(),
+                   "workspace_bytes": lik.workspace_bytes(W.n_data, W.n_mc),
+                   "workspace_bytes_per_event": round(lik.workspace_bytes(W.n_data, W.n_mc)
+                                                      / (W.n_data + W.n_mc), 1)},
         "roofline": roof,
     }
     result["entry_points"] = entry_point_times(lik, th, v)
@@ -336,6 +380,7 @@ def main():
         print("[bench] batched path done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(W, data, mc)
+        result["cpu_all_cores"] = cpu_all_cores(W, data, mc)
     print(json.dumps(result), flush=True)
 
 
