@@ -153,25 +153,76 @@ def cpu_all_cores(W, data, mc, n_data=200_000, n_mc=1_000_000):
                       f"in {cores} processes (eq. (4)-(7) combine); {dt:.2f} s"}
 
 
-def fit_compare(lik, W, cap_s=60.0):
-    """Newton-CG time to minimum from a fixed start, with FP64 HVPs and with
-    FP32 HVPs inside CG (line search and convergence test in FP64 in both),
-    for scipy's forcing term (the paper's fits) and for the relative one."""
+def fit_compare(lik, W, cap_s=60.0, n_starts=5):
+    """Newton-CG time to minimum from seeded starts near the generating
+    parameters, with FP64 HVPs and with FP32 HVPs inside CG (line search and
+    convergence test in FP64 in both), for scipy's forcing term (the paper's
+    fits) and for the relative one.  Per forcing rule: the first start in
+    detail, and the totals over n_starts starts."""
     import synth
-    start = W.theta_true + synth.rng_for(1, synth.configs.STREAM_TEST).normal(
-        scale=np.tile([0.02, 0.02, 0.002, 0.002], W.n_res))
+    rng = synth.rng_for(1, synth.configs.STREAM_TEST)
+    starts = [W.theta_true + rng.normal(scale=np.tile([0.02, 0.02, 0.002, 0.002], W.n_res))
+              for _ in range(n_starts)]
     out = {}
     for forcing in ("relative", "scipy"):
         rec = {}
         for prec in ("f64", "f32"):
-            th, rep = lik.fit(start, xtol=1e-8, maxiter=200, time_cap_s=cap_s, hvp_precision=prec,
-                              forcing=forcing)
-            rec[prec] = {"seconds": round(rep["seconds"], 4), "nll": rep["nll"],
-                         "iterations": rep["iterations"], "hvps": rep["n_hvp"],
-                         "grads": rep["n_grad"], "nlls": rep["n_nll"], "converged": rep["converged"]}
+            runs = []
+            for i, start in enumerate(starts):
+                th, rep = lik.fit(start, xtol=1e-8, maxiter=200, time_cap_s=cap_s,
+                                  hvp_precision=prec, forcing=forcing)
+                runs.append(rep)
+            r0 = runs[0]
+            rec[prec] = {"seconds": round(r0["seconds"], 4), "nll": r0["nll"],
+                         "iterations": r0["iterations"], "hvps": r0["n_hvp"],
+                         "grads": r0["n_grad"], "nlls": r0["n_nll"], "converged": r0["converged"],
+                         f"seconds_total_{n_starts}_starts": round(sum(r["seconds"] for r in runs), 4),
+                         f"iterations_total_{n_starts}_starts": int(sum(r["iterations"] for r in runs)),
+                         f"converged_{n_starts}_starts": int(sum(r["converged"] for r in runs)),
+                         "nll_spread": float(max(r["nll"] for r in runs) - min(r["nll"] for r in runs))}
         rec["speedup_mixed_vs_fp64"] = round(rec["f64"]["seconds"] / max(rec["f32"]["seconds"], 1e-9), 3)
+        key = f"seconds_total_{n_starts}_starts"
+        rec[f"speedup_mixed_vs_fp64_{n_starts}_starts"] = round(rec["f64"][key] / max(rec["f32"][key], 1e-9), 3)
         rec["nll_diff_mixed_minus_fp64"] = rec["f32"]["nll"] - rec["f64"]["nll"]
         out[f"forcing_{forcing}"] = rec
+    return out
+
+
+def k30_bench(steps=20):
+    """The differentiation workload (K = 30, 4M data + 20M MC): fused
+    NLL+grad+HVP events/s on the FP64 and FP32 streams."""
+    import torch
+    import synth
+    from paper_2403_09225_amd import Likelihood
+    W = synth.workload(3)
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(3, synth.configs.STREAM_MC))
+    data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
+                               synth.rng_for(3, synth.configs.STREAM_DATA))
+    lik = Likelihood(W.channel, W.spin, streams=("f64", "f32")).bind(data[0], data[1], mc[0], mc[1])
+    del data, mc
+    th = torch.tensor(W.theta_true, dtype=torch.float64, device="cuda")
+    v = torch.tensor(np.random.Generator(np.random.PCG64(3)).normal(size=W.n_par),
+                     dtype=torch.float64, device="cuda")
+    n = W.n_data + W.n_mc
+    out = {"workload": f"K={W.n_res} (P={W.n_par}), {W.n_data} data + {W.n_mc} MC events"}
+    for prec in ("f64", "f32"):
+        lik.set_precision(prec)
+        for _ in range(3):
+            lik.hvp(th, v)
+        torch.cuda.synchronize()
+        lik.set_kernel_timing(True)
+        lik.kernel_time()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lik.hvp(th, v)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        k_ms, k_n = lik.kernel_time()
+        lik.set_kernel_timing(False)
+        out[prec] = {"ms_per_step": round(dt * 1e3, 4), "events_per_s": round(n / dt, 1),
+                     "kernel_us": round(k_ms / max(k_n, 1) * 1e3, 2),
+                     "hbm_frac_kernel": round(n * 18 * (8 if prec == "f64" else 4)
+                                              / (k_ms / max(k_n, 1) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     return out
 
 
@@ -268,6 +319,7 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--shape", default="", help="layout,groups,res_per_group override (layout 0: lanes per event, 1: waves per block)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-k30", action="store_true", help="skip the K = 30, 24M-event section")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -285,7 +337,13 @@ def main():
     print(f"[bench] workload ready: {W.n_data} data + {W.n_mc} MC events, K={W.n_res}",
           file=sys.stderr, flush=True)
     lik = Likelihood(W.channel, W.spin, streams=("f64", "f32"))
-    lik.bind(data[0], data[1], mc[0], mc[1])
+    dev = [torch.as_tensor(x, device="cuda") for x in (data[0], data[1], mc[0], mc[1])]
+    torch.cuda.synchronize()
+    t_bind = time.perf_counter()
+    lik.bind(*dev)
+    torch.cuda.synchronize()
+    t_bind = time.perf_counter() - t_bind
+    del dev
     if args.shape:
         lik.set_launch_shape(*[int(x) for x in args.shape.split(",")])
     lik.set_precision(args.precision)
@@ -347,6 +405,7 @@ def main():
                    "n_res": W.n_res, "n_data": W.n_data, "n_mc": W.n_mc,
                    "launch_shape": args.shape or "auto", "grid_blocks": lik.grid_blocks(),
                    "workspace_bytes": lik.workspace_bytes(W.n_data, W.n_mc),
+                   "bind_precompute_ms": round(t_bind * 1e3, 3),
                    "workspace_bytes_per_event": round(lik.workspace_bytes(W.n_data, W.n_mc)
                                                       / (W.n_data + W.n_mc), 1)},
         "roofline": roof,
@@ -373,11 +432,17 @@ def main():
     if not args.no_fit:
         result["newton_cg_time_to_min"] = fit_compare(lik, W)
         print("[bench] fits done", file=sys.stderr, flush=True)
-    if not args.no_batched:
+    if not args.no_batched or not args.no_k30:
         del lik
         torch.cuda.empty_cache()
+    if not args.no_batched:
         result["batched_multistart"] = batched_bench()
+        torch.cuda.empty_cache()
         print("[bench] batched path done", file=sys.stderr, flush=True)
+    if not args.no_k30:
+        result["k30_differentiation"] = k30_bench()
+        torch.cuda.empty_cache()
+        print("[bench] K = 30 workload done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(W, data, mc)
         result["cpu_all_cores"] = cpu_all_cores(W, data, mc)

@@ -103,8 +103,9 @@ bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 // Automatic launch shape.  Layout 2 (a block of G waves shares each batch of
 // 64 events, wave g owns R resonances) keeps the resonance table and plane
 // pointers in scalar registers; the choice covers K with the fewest padded
-// resonance slots at R <= 3 (FP64 moment accumulators: 18 R per lane).
-// Layout 1 (T lanes of a wave share an event) serves K > 24.
+// resonance slots at R <= 3 (FP64 moment accumulators: 18 R per lane), and
+// 8 waves of 4 resonances (one block per CU) for 24 < K <= 32.  Layout 1
+// (T lanes of a wave share an event) serves K > 32.
 void auto_shape(int K, int& L, int& T, int& R) {
   L = 2;
   if (K <= 2) { T = 1; R = 2; return; }
@@ -114,8 +115,8 @@ void auto_shape(int K, int& L, int& T, int& R) {
   if (K <= 12) { T = 4; R = 3; return; }
   if (K <= 16) { T = 8; R = 2; return; }
   if (K <= 24) { T = 12; R = 2; return; }
+  if (K <= 32) { T = 8; R = 4; return; }
   L = 1;
-  if (K <= 32) { T = 16; R = 2; return; }
   T = 32; R = 2;
 }
 

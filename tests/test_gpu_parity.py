@@ -54,7 +54,7 @@ def test_fp64_parity(K, nd, nm, seed, wm):
 
 @pytest.mark.parametrize("shape", [(1, 4, 3), (1, 4, 4), (1, 8, 2), (1, 8, 4), (1, 16, 2),
                                    (1, 16, 4), (1, 32, 2), (2, 4, 3), (2, 3, 4), (2, 6, 2),
-                                   (2, 8, 2), (2, 8, 3), (2, 12, 2)])
+                                   (2, 8, 2), (2, 8, 3), (2, 8, 4), (2, 12, 2)])
 def test_every_launch_shape(shape):
     say(f"[shape] K=12 layout,groups,R={shape}")
     model, th, data, mc, v = case(12, 1777, 6001, 20)
@@ -67,7 +67,8 @@ def test_every_launch_shape(shape):
                                      (6, (1, 4, 2)), (16, (1, 4, 4)), (30, (1, 16, 2)),
                                      (64, (1, 32, 2)), (2, (2, 1, 2)), (3, (2, 1, 4)), (5, (2, 2, 3)),
                                      (7, (2, 2, 4)), (8, (2, 4, 2)), (16, (2, 8, 2)), (22, (2, 8, 3)),
-                                     (15, (2, 5, 3)), (24, (2, 12, 2)), (12, (2, 3, 4))])
+                                     (15, (2, 5, 3)), (24, (2, 12, 2)), (12, (2, 3, 4)),
+                                     (30, (2, 8, 4)), (25, (2, 8, 4))])
 def test_small_k_shapes(K, shape):
     say(f"[shape] K={K} layout,groups,R={shape}")
     model, th, data, mc, v = case(K, 913, 3007, 21 + K)
