@@ -223,6 +223,49 @@ typedef struct pwa_fit_report {
 int pwa_fit(pwa_ctx* ctx, double* d_theta_inout, const pwa_fit_opts* h_opts,
             pwa_fit_report* h_rep, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * At a minimum: error matrix and fit fractions.  The paper quotes a fit
+ * fraction per resonance (Table 1, column F_i) without defining it; here it
+ * is the usual phase-space integral ratio, estimated with the bound MC
+ * events (efficiency 1):
+ *   F_k = sum_MC |c_k a_k|^2 / sum_MC |sum_l c_l a_l|^2,
+ * so the F_k need not add up to 1 (interference).  Parameter errors are the
+ * inverse Hessian of NLL = -ln L (eq. (3)).
+ * ------------------------------------------------------------------------- */
+
+/* Hessian d^2 NLL / dtheta^2 at theta: P forward-over-reverse passes (the
+ * Hessian-vector product of eq. (7)) along the unit vectors, symmetrised as
+ * (H + H^T)/2.  d_H: device, caller-owned, P*P doubles, row-major.  Uses the
+ * event stream of the current precision; stream-ordered.
+ * Errors: PWA_E_INVALID, PWA_E_STATE (unbound), PWA_E_HIP. */
+int pwa_hessian(pwa_ctx* ctx, const double* d_theta, double* d_H, hipStream_t stream);
+
+/* Fit fractions F_k (definition above; d_ff: K doubles) and, if d_dff is not
+ * null, their gradients dF_k/dtheta (d_dff: K x P doubles, row-major), from
+ * K + 1 gradient passes over the MC events only: one per resonance with the
+ * other couplings set to zero (G_k = sum_MC |c_k a_k|^2 and its gradient)
+ * and one with all of them (G).  Device buffers, caller-owned; uses the
+ * current precision's stream; stream-ordered.  If G = 0 (all couplings zero)
+ * the outputs are not finite.  Errors: PWA_E_INVALID, PWA_E_STATE, PWA_E_HIP. */
+int pwa_fit_fractions(pwa_ctx* ctx, const double* d_theta, double* d_ff, double* d_dff,
+                      hipStream_t stream);
+
+/* Covariance matrix of the free parameters (host arrays, P x P row-major):
+ * the inverse of H restricted to the rows and columns i with h_free[i] != 0
+ * (all of them if h_free is null), by a Cholesky factorisation of that
+ * block; rows and columns of fixed parameters are zero.  The NLL does not
+ * change when every coupling is multiplied by one complex number, so with
+ * all parameters free H is singular: fix one coupling (its real and
+ * imaginary parts).  Errors: PWA_E_INVALID (sizes, null, non-finite H),
+ * PWA_E_DOMAIN (the free block is not positive definite). */
+int pwa_covariance(int32_t P, const double* h_H, const uint8_t* h_free, double* h_cov);
+
+/* Linear error propagation (host arrays): sigma_r = sqrt(J_r C J_r^T) for the
+ * n rows of J (n x P, row-major), e.g. the fit-fraction gradients, with the
+ * covariance C (P x P).  A negative quadratic form gives NaN.
+ * Errors: PWA_E_INVALID. */
+int pwa_propagate(int32_t P, int32_t n, const double* h_J, const double* h_cov, double* h_sigma);
+
 /* Reads and clears the context's sticky device status word (synchronises
  * the stream).  Bits: 1 = a resonance mass at or below threshold was seen,
  * 2 = a non-finite NLL was produced.  Negative on error. */

@@ -10,4 +10,5 @@ from .pwa_oracle import (  # noqa: F401
     Dual, DomainError, new_tag, primal, kallen, kinematics, barrier, legendre,
     breakup_sq, amplitude, amplitudes, intensity, nll, partials, combine, grad,
     hvp, hessian, grad_scale, gram, round_to, nll_batched, newton_cg_fit,
+    fraction_matrix, fit_fractions,
 )

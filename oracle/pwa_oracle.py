@@ -574,6 +574,85 @@ def nll_batched(data, mc, model, theta, C, fmt="f64", chunk=50_000, parts=False)
 
 
 # --------------------------------------------------------------------------
+# At the minimum: fit fractions (Table 1 quotes F_i per resonance without a
+# definition; read here as the ratio of phase-space integrals, estimated by
+# the MC sample) and the interference terms.
+# --------------------------------------------------------------------------
+def fraction_matrix(mc, model, theta, chunk=100_000):
+    """K x K matrix Phi with, for y_k = c_k a_k and D = sum_MC |sum_k y_k|^2,
+        Phi[k, k] = sum_MC |y_k|^2 / D                     (fit fraction F_k)
+        Phi[k, l] = sum_MC 2 Re(conj(y_k) y_l) / D, k < l  (interference)
+    and zero below the diagonal.  Per chunk the sums over events are one
+    matrix product Y^H Y (Y: events x K); chunk sums are added with
+    math.fsum."""
+    theta = np.asarray(theta, dtype=np.float64)
+    K = len(model.channel)
+    m_parts, d_parts = [], []
+    for ev in _chunks(mc, chunk):
+        if not len(ev[0]):
+            continue
+        a = amplitudes(ev, model, theta)
+        Y = np.stack([(theta[4 * k] + 1j * theta[4 * k + 1]) * a[k] for k in range(K)], axis=1)
+        m_parts.append(Y.conj().T @ Y)
+        d_parts.append(math.fsum(np.abs(Y.sum(axis=1)) ** 2))
+    D = math.fsum(d_parts)
+    Phi = np.zeros((K, K))
+    for k in range(K):
+        Phi[k, k] = math.fsum(m[k, k].real for m in m_parts) / D
+        for l in range(k + 1, K):
+            Phi[k, l] = 2.0 * math.fsum(m[k, l].real for m in m_parts) / D
+    return Phi
+
+
+def fit_fractions(mc, model, theta, chunk=100_000):
+    """F_k = sum_MC |c_k a_k|^2 / sum_MC |sum_l c_l a_l|^2 and the gradients
+    dF_k/dtheta (K x P).  Chain rule per event: d|y|^2 = 2 Re(conj(y) dy)
+    with dy/dRe c = a, dy/dIm c = i a, dy/dM = c da/dM, dy/dGamma = c da/dGamma
+    (the a-derivatives by dual numbers); then
+    dF_k = dN_k / D - N_k dD / D^2.  Event sums by math.fsum per chunk, chunk
+    sums by math.fsum."""
+    theta = np.asarray(theta, dtype=np.float64)
+    K = len(model.channel)
+    P = 4 * K
+    n_parts = [[] for _ in range(K)]
+    dn_parts = [[] for _ in range(P)]   # entry 4k + i: d N_k / d theta_{4k+i}
+    d_parts = []
+    dd_parts = [[] for _ in range(P)]
+    for ev in _chunks(mc, chunk):
+        if not len(ev[0]):
+            continue
+        kin = _kin_all(ev, model)
+        y, cols = [], []
+        for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
+            c = theta[4 * k] + 1j * theta[4 * k + 1]
+            M, G = theta[4 * k + 2], theta[4 * k + 3]
+            am = amplitude(kin[ch], ch, J, Dual(M, 1.0, new_tag()), G, model)
+            ag = amplitude(kin[ch], ch, J, M, Dual(G, 1.0, new_tag()), model)
+            a = am.a
+            y.append(c * a)
+            cols.append([a, 1j * a, c * am.b, c * ag.b])
+        z = sum(y)
+        d_parts.append(math.fsum(np.abs(z) ** 2))
+        for k in range(K):
+            n_parts[k].append(math.fsum(np.abs(y[k]) ** 2))
+            for i in range(4):
+                dn_parts[4 * k + i].append(math.fsum(2.0 * (np.conj(y[k]) * cols[k][i]).real))
+                dd_parts[4 * k + i].append(math.fsum(2.0 * (np.conj(z) * cols[k][i]).real))
+    D = math.fsum(d_parts)
+    dD = np.array([math.fsum(t) for t in dd_parts])
+    F = np.zeros(K)
+    dF = np.zeros((K, P))
+    for k in range(K):
+        N = math.fsum(n_parts[k])
+        F[k] = N / D
+        dN = np.zeros(P)
+        for i in range(4):
+            dN[4 * k + i] = math.fsum(dn_parts[4 * k + i])
+        dF[k] = dN / D - N * dD / (D * D)
+    return F, dF
+
+
+# --------------------------------------------------------------------------
 # Reference fit: the paper's optimiser (scipy Newton-CG, Sec. 3).
 # --------------------------------------------------------------------------
 def newton_cg_fit(data, mc, model, theta0, xtol=1e-8, maxiter=200, chunk=100_000):

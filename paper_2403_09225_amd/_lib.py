@@ -78,6 +78,10 @@ SIGNATURES = {
     "pwa_freeze": (c_int32, [_P, _P, c_int32, c_int32, _P, c_size_t, _P]),
     "pwa_nll_batched": (c_int32, [_P, _P, c_int32, _P, _P]),
     "pwa_gram": (c_int32, [_P, _P, _P]),
+    "pwa_hessian": (c_int32, [_P, _P, _P, _P]),
+    "pwa_fit_fractions": (c_int32, [_P, _P, _P, _P, _P]),
+    "pwa_covariance": (c_int32, [c_int32, _P, _P, _P]),
+    "pwa_propagate": (c_int32, [c_int32, c_int32, _P, _P, _P]),
     # include/pwa_mlp.h
     "pwa_hist2d": (c_int32, [_P, _P, _P, c_int32, c_double, ctypes.POINTER(c_double), _P, _P]),
     "pwa_mlp_n_params": (c_int64, [ctypes.POINTER(PwaMlpDims)]),

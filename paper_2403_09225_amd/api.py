@@ -207,6 +207,32 @@ class Likelihood:
         L.check("pwa_gram", self.lib.pwa_gram(self._h, _ptr(out), _stream()))
         return torch.view_as_complex(out.view(self.n_res, self.n_res, 2))
 
+    # ------------------------------------------------------ at the minimum
+    def hessian(self, theta):
+        """Symmetrised P x P Hessian of the NLL (P Hessian-vector passes)."""
+        t = self._theta(theta)
+        out = torch.empty((self.n_par, self.n_par), dtype=torch.float64, device=self.device)
+        L.check("pwa_hessian", self.lib.pwa_hessian(self._h, _ptr(t), _ptr(out), _stream()))
+        return out
+
+    def fit_fractions(self, theta, with_grad=True):
+        """F_k = sum_MC |c_k a_k|^2 / sum_MC |z|^2 and (with_grad) dF_k/dtheta (K x P)."""
+        t = self._theta(theta)
+        ff = torch.empty(self.n_res, dtype=torch.float64, device=self.device)
+        dff = (torch.empty((self.n_res, self.n_par), dtype=torch.float64, device=self.device)
+               if with_grad else None)
+        L.check("pwa_fit_fractions", self.lib.pwa_fit_fractions(
+            self._h, _ptr(t), _ptr(ff), _ptr(dff), _stream()))
+        return (ff, dff) if with_grad else ff
+
+    def errors(self, theta, free_mask=None):
+        """Covariance of the free parameters, parameter errors, fit fractions
+        and their propagated errors at theta (normally a fitted minimum).
+        Returns a dict of host arrays."""
+        H = self.hessian(theta)
+        ff, dff = self.fit_fractions(theta)
+        return errors_from(H.cpu().numpy(), ff.cpu().numpy(), dff.cpu().numpy(), free_mask)
+
     # ------------------------------------------------------------------- fit
     def fit(self, theta0, xtol=1e-8, maxiter=200, cg_maxiter=0, time_cap_s=0.0,
             hvp_precision="f64", free_mask=None, forcing="scipy"):
@@ -246,3 +272,37 @@ def combine(parts, n_par, n_data_total, n_mc_total, v=None, device="cuda"):
         ctypes.c_void_p(base), ctypes.c_void_p(base + 8),
         ctypes.c_void_p(base + 8 * (1 + n_par)) if v is not None else None, _stream()))
     return out[0], out[1:1 + n_par], (out[1 + n_par:] if v is not None else None)
+
+
+def covariance(H, free_mask=None):
+    """Inverse of the Hessian's free block (pwa_covariance); host arrays."""
+    lib = L.load()
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    P = H.shape[0]
+    cov = np.empty((P, P))
+    fm = None
+    if free_mask is not None:
+        fm = np.ascontiguousarray(np.asarray(free_mask, dtype=bool), dtype=np.uint8)
+    L.check("pwa_covariance", lib.pwa_covariance(
+        P, H.ctypes.data_as(ctypes.c_void_p),
+        fm.ctypes.data_as(ctypes.c_void_p) if fm is not None else None,
+        cov.ctypes.data_as(ctypes.c_void_p)))
+    return cov
+
+
+def propagate(J, cov):
+    """sigma_r = sqrt(J_r C J_r^T) for the rows of J (pwa_propagate)."""
+    lib = L.load()
+    J = np.ascontiguousarray(np.atleast_2d(J), dtype=np.float64)
+    cov = np.ascontiguousarray(cov, dtype=np.float64)
+    sig = np.empty(J.shape[0])
+    L.check("pwa_propagate", lib.pwa_propagate(
+        cov.shape[0], J.shape[0], J.ctypes.data_as(ctypes.c_void_p),
+        cov.ctypes.data_as(ctypes.c_void_p), sig.ctypes.data_as(ctypes.c_void_p)))
+    return sig
+
+
+def errors_from(H, ff, dff, free_mask=None):
+    cov = covariance(H, free_mask)
+    return {"hessian": H, "covariance": cov, "sigma": np.sqrt(np.clip(np.diag(cov), 0, None)),
+            "fit_fractions": ff, "fit_fraction_sigma": propagate(dff, cov)}

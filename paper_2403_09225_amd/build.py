@@ -4,7 +4,8 @@
 
 Compiles csrc/pwa_kernels.hip (likelihood kernels and launchers),
 csrc/pwa_batched.hip (fixed-lineshape batched path on the matrix cores),
-csrc/pwa_mlp.hip (histograms and the start-proposal MLP) and
+csrc/pwa_mlp.hip (histograms and the start-proposal MLP),
+csrc/pwa_analysis.hip (Hessian columns and fit fractions at a minimum) and
 csrc/pwa_api.cpp (C ABI, workspace layout, Newton-CG driver) with hipcc and
 links them into paper_2403_09225_amd/libpwa.so.
 """
@@ -47,9 +48,11 @@ def build(verbose=False, jobs=2):
     b_obj = os.path.join(bdir, "pwa_batched.o")
     a_obj = os.path.join(bdir, "pwa_api.o")
     m_obj = os.path.join(bdir, "pwa_mlp.o")
+    x_obj = os.path.join(bdir, "pwa_analysis.o")
     cmds = [
         [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_mlp.hip"), "-o", m_obj],
         [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_kernels.hip"), "-o", k_obj],
+        [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_analysis.hip"), "-o", x_obj],
         [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_batched.hip"), "-o", b_obj],
         [HIPCC] + COMMON + DEVICE + ["-x", "hip", "-c", os.path.join(CSRC, "pwa_api.cpp"), "-o", a_obj],
     ]
@@ -63,7 +66,8 @@ def build(verbose=False, jobs=2):
             sys.stderr.write(out + err)
             raise RuntimeError("hipcc failed for " + c[-3])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, b_obj, a_obj, m_obj], verbose)
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, b_obj, a_obj, m_obj, x_obj],
+         verbose)
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} in {time.time() - t0:.1f} s", flush=True)

@@ -8,6 +8,7 @@
 #include <new>
 #include <vector>
 
+#include "pwa_analysis.h"
 #include "pwa_batched.h"
 #include "pwa_internal.h"
 
@@ -190,9 +191,11 @@ int fold_timing(pwa_ctx* c) {
   return PWA_OK;
 }
 
+// One evaluation: table, pass, reduction and finaliser.  With mc_only the
+// grid covers the MC events alone (the data sums come out as zero).
 int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta,
              const double* d_v, double* d_nll, double* d_grad, double* d_hv, double* d_dd,
-             hipStream_t st) {
+             hipStream_t st, bool mc_only = false) {
   int L = 2, T = 1, R = 1;
   shape_of(c, mode, L, T, R);
   const int kslots = T * R;
@@ -208,6 +211,10 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
   a.n_data = c->n_data;
   a.n_mc = c->n_mc;
   split_blocks(c, mode, nb, a.nb_data, a.nb_mc);
+  if (mc_only) {
+    a.nb_data = 0;
+    a.nb_mc = nb;
+  }
   a.K = c->K;
   a.part = c->part;
   const bool timed = c->timing;
@@ -921,6 +928,111 @@ int pwa_gram(pwa_ctx* c, double* d_gram, hipStream_t st) {
                         hipMemcpyDeviceToDevice, st) == hipSuccess
              ? PWA_OK
              : PWA_E_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// At the minimum: Hessian, covariance, fit fractions, error propagation.
+// ---------------------------------------------------------------------------
+
+// Scratch slots (the fit driver uses [0, 4P + 1)).
+static double* unit_slot(pwa_ctx* c) { return c->scratch + 5 * c->P; }
+static double* mask_slot(pwa_ctx* c) { return c->scratch + 6 * c->P; }
+
+int pwa_hessian(pwa_ctx* c, const double* d_theta, double* d_H, hipStream_t st) {
+  if (!c || !d_theta || !d_H) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  const int P = c->P;
+  double* d_e = unit_slot(c);
+  for (int j = 0; j < P; ++j) {
+    if (launch_unit(d_e, P, j, st) != hipSuccess) return PWA_E_HIP;
+    const int r = run_eval(c, MODE_HVP, OUT_COMBINED, c->precision, d_theta, d_e, nullptr, nullptr,
+                           d_H + (size_t)j * P, nullptr, st);
+    if (r != PWA_OK) return r;
+  }
+  return launch_symmetrise(d_H, P, st) == hipSuccess ? PWA_OK : PWA_E_HIP;
+}
+
+int pwa_fit_fractions(pwa_ctx* c, const double* d_theta, double* d_ff, double* d_dff,
+                      hipStream_t st) {
+  if (!c || !d_theta || !d_ff) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  const int K = c->K, P = c->P;
+  double* d_m = mask_slot(c);
+  for (int k = 0; k < K; ++k) {
+    if (launch_mask(d_theta, d_m, K, k, st) != hipSuccess) return PWA_E_HIP;
+    const int r = run_eval(c, MODE_GRAD, OUT_PARTIALS, c->precision, d_m, nullptr, nullptr,
+                           nullptr, nullptr, c->dd, st, true);
+    if (r != PWA_OK) return r;
+    if (launch_ff_take(c->dd, P, k, d_ff, d_dff, st) != hipSuccess) return PWA_E_HIP;
+  }
+  const int r = run_eval(c, MODE_GRAD, OUT_PARTIALS, c->precision, d_theta, nullptr, nullptr,
+                         nullptr, nullptr, c->dd, st, true);
+  if (r != PWA_OK) return r;
+  return launch_ff_finish(c->dd, K, P, d_ff, d_dff, st) == hipSuccess ? PWA_OK : PWA_E_HIP;
+}
+
+int pwa_covariance(int32_t P, const double* H, const uint8_t* free_mask, double* cov) {
+  if (P < 1 || P > 4 * PWA_MAX_RES || !H || !cov) return PWA_E_INVALID;
+  std::vector<int> idx;
+  for (int i = 0; i < P; ++i)
+    if (!free_mask || free_mask[i]) idx.push_back(i);
+  for (int i = 0; i < P * P; ++i)
+    if (!isfinite(H[i])) return PWA_E_INVALID;
+  const int n = (int)idx.size();
+  for (int i = 0; i < P * P; ++i) cov[i] = 0.0;
+  if (n == 0) return PWA_OK;
+  // Cholesky factor of the free block, A = L L^T (lower triangle of L).
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = H[(size_t)idx[j] * P + idx[j]];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0.0)) return PWA_E_DOMAIN;
+    const double ljj = sqrt(d);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double a = 0.5 * (H[(size_t)idx[i] * P + idx[j]] + H[(size_t)idx[j] * P + idx[i]]);
+      for (int k = 0; k < j; ++k) a -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = a / ljj;
+    }
+  }
+  // A^{-1} column by column: solve L y = e_j, then L^T x = y.
+  std::vector<double> y(n), x(n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) {
+      double a = (i == j) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) a -= L[(size_t)i * n + k] * y[k];
+      y[i] = a / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double a = y[i];
+      for (int k = i + 1; k < n; ++k) a -= L[(size_t)k * n + i] * x[k];
+      x[i] = a / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) cov[(size_t)idx[i] * P + idx[j]] = x[i];
+  }
+  // exact symmetry (the two triangular solves round differently)
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const size_t a = (size_t)idx[i] * P + idx[j], b = (size_t)idx[j] * P + idx[i];
+      const double m = 0.5 * (cov[a] + cov[b]);
+      cov[a] = cov[b] = m;
+    }
+  return PWA_OK;
+}
+
+int pwa_propagate(int32_t P, int32_t n, const double* J, const double* cov, double* sigma) {
+  if (P < 1 || n < 0 || (n > 0 && (!J || !cov || !sigma))) return PWA_E_INVALID;
+  for (int r = 0; r < n; ++r) {
+    const double* g = J + (size_t)r * P;
+    double q = 0.0;
+    for (int i = 0; i < P; ++i) {
+      double a = 0.0;
+      for (int j = 0; j < P; ++j) a += cov[(size_t)i * P + j] * g[j];
+      q += g[i] * a;
+    }
+    sigma[r] = q >= 0.0 ? sqrt(q) : NAN;
+  }
+  return PWA_OK;
 }
 
 }  // extern "C"

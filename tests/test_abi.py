@@ -121,6 +121,10 @@ def test_unbound_and_bad_bind_arguments(lib):
         assert lib.pwa_hvp(h, fake, fake, fake, None, None, st) == L.PWA_E_STATE
         assert lib.pwa_partials(h, fake, None, fake, st) == L.PWA_E_STATE
         assert lib.pwa_intensity(h, fake, 0, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_hessian(h, fake, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_hessian(h, None, fake, st) == L.PWA_E_INVALID
+        assert lib.pwa_fit_fractions(h, fake, fake, None, st) == L.PWA_E_STATE
+        assert lib.pwa_fit_fractions(h, fake, None, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_intensity(h, fake, 2, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_intensity(h, None, 0, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_device_status(h, st) == L.PWA_E_STATE
@@ -200,3 +204,64 @@ def test_event_count_limit(lib):
         assert lib.pwa_bind(h, fake, fake, lim, fake, fake, 10, fake, 1 << 40, None) == L.PWA_E_INVALID
     finally:
         lib.pwa_destroy(h)
+
+
+# ------------------------------------------------ host-only error matrix
+def _spd(P, seed):
+    import numpy as np
+    r = np.random.Generator(np.random.PCG64(seed))
+    A = r.normal(size=(P, P))
+    return A @ A.T + P * np.eye(P)
+
+
+def test_covariance_is_inverse_of_free_block():
+    """pwa_covariance (Cholesky on the host) against numpy's inverse of the
+    free block; fixed rows and columns are zero and the result is exactly
+    symmetric."""
+    import numpy as np
+    from paper_2403_09225_amd.api import covariance
+    for P, seed in ((4, 1), (12, 2), (48, 3), (120, 4)):
+        H = _spd(P, seed)
+        free = np.random.Generator(np.random.PCG64(seed + 10)).random(P) > 0.2
+        C = covariance(H, free)
+        ref = np.zeros((P, P))
+        ref[np.ix_(free, free)] = np.linalg.inv(H[np.ix_(free, free)])
+        np.testing.assert_allclose(C, ref, rtol=1e-10, atol=1e-13 * np.max(np.abs(ref)))
+        assert np.array_equal(C, C.T)
+        np.testing.assert_allclose(covariance(H), np.linalg.inv(H), rtol=1e-10,
+                                   atol=1e-13 * np.max(np.abs(np.linalg.inv(H))))
+
+
+def test_covariance_errors(lib):
+    import numpy as np
+    from paper_2403_09225_amd.api import covariance
+    H = _spd(8, 5)
+    H[3, 3] = -1.0                       # not positive definite
+    with pytest.raises(L.PwaError):
+        covariance(H)
+    fm = np.ones(8, bool)
+    fm[3] = False
+    covariance(H, fm)                    # fine once that parameter is fixed
+    Hn = _spd(8, 6)
+    Hn[1, 2] = np.nan
+    out = np.empty((8, 8))
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    assert lib.pwa_covariance(8, ptr(Hn), None, ptr(out)) == L.PWA_E_INVALID
+    assert lib.pwa_covariance(0, ptr(Hn), None, ptr(out)) == L.PWA_E_INVALID
+    assert lib.pwa_covariance(8, None, None, ptr(out)) == L.PWA_E_INVALID
+    # the likelihood's symmetry makes the all-free Hessian singular; with a
+    # zero mode pushed slightly negative by rounding, Cholesky must refuse
+    A = np.random.Generator(np.random.PCG64(7)).normal(size=(8, 7))
+    u = np.linalg.svd(A.T)[2][-1]            # null vector of A^T
+    Z = np.ascontiguousarray(A @ A.T - 1e-9 * np.outer(u, u))
+    assert lib.pwa_covariance(8, ptr(Z), None, ptr(out)) == L.PWA_E_DOMAIN
+
+
+def test_propagate():
+    import numpy as np
+    from paper_2403_09225_amd.api import propagate
+    C = np.linalg.inv(_spd(10, 8))
+    J = np.random.Generator(np.random.PCG64(9)).normal(size=(4, 10))
+    np.testing.assert_allclose(propagate(J, C), np.sqrt(np.einsum("ri,ij,rj->r", J, C, J)),
+                               rtol=1e-13)
+    assert propagate(np.zeros((1, 10)), C)[0] == 0.0
