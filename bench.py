@@ -253,6 +253,26 @@ def entry_point_times(lik, th, v, reps=20):
     return out
 
 
+def at_minimum_times(lik, th, reps=3):
+    """Wall time of the quantities read off at a minimum on the same events:
+    the full Hessian (pwa_hessian, P Hessian-vector passes) and the fit
+    fractions with their gradients (pwa_fit_fractions, K + 1 MC-only
+    gradient passes), FP64 event stream."""
+    import torch
+    lik.set_precision("f64")
+    out = {}
+    for name, fn in (("hessian", lambda: lik.hessian(th)),
+                     ("fit_fractions", lambda: lik.fit_fractions(th))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = round((time.perf_counter() - t0) / reps * 1e3, 3)
+    return out
+
+
 def batched_bench(reps=5):
     """Fixed-lineshape batched multi-start (K = 20, 2M data, 10M MC, 256
     coupling vectors): time per batch and NLL error per operand format (vs
@@ -411,6 +431,7 @@ def main():
         "roofline": roof,
     }
     result["entry_points"] = entry_point_times(lik, th, v)
+    result["at_minimum"] = at_minimum_times(lik, th)
     lik.set_precision(args.precision)
     # A plain 1 GiB device-to-device copy: the practical HBM ceiling (read +
     # write bytes / time) and the reference for the HBM byte counters.
