@@ -227,15 +227,18 @@ def k30_bench(steps=20):
 
 
 def entry_point_times(lik, th, v, reps=20):
-    """Per-call time of pwa_nll, pwa_grad and pwa_hvp (FP64 and FP32 event
-    streams): wall time per call over `reps` back-to-back calls and the
+    """Per-call time of pwa_nll, pwa_grad, pwa_hvp and pwa_hvp_reuse (an HVP
+    at the theta of the last pwa_hvp, as inside CG) on the FP64 and FP32
+    event streams: wall time per call over `reps` back-to-back calls and the
     average duration of the per-event kernel (HIP events on its stream)."""
     import torch
     out = {}
     for prec in ("f64", "f32"):
         lik.set_precision(prec)
         for name, fn in (("nll", lambda: lik.nll(th)), ("grad", lambda: lik.grad(th)),
-                         ("hvp", lambda: lik.hvp(th, v))):
+                         ("hvp", lambda: lik.hvp(th, v)), ("hvp_reuse", lambda: lik.hvp_reuse(v))):
+            if name == "hvp_reuse":
+                lik.hvp(th, v)   # the theta-only totals the reuse pass starts from
             for _ in range(3):
                 fn()
             torch.cuda.synchronize()

@@ -148,6 +148,22 @@ int pwa_grad(pwa_ctx* ctx, const double* d_theta, double* d_nll, double* d_grad,
 int pwa_hvp(pwa_ctx* ctx, const double* d_theta, const double* d_v, double* d_hv,
             double* d_nll, double* d_grad, hipStream_t stream);
 
+/* Hessian-vector product at the theta of the last pwa_hvp call on this
+ * context, for a new direction d_v (P doubles): Newton-CG evaluates many
+ * products at one theta.  Of the per-resonance event moments that the
+ * eq. (7) product is contracted from, only the three weighted by the
+ * direction (the derivative of z along v) depend on v; this pass
+ * accumulates those alone and reuses the theta-only totals of that call, so
+ * it does about half the per-event work.  Results equal pwa_hvp at that
+ * theta up to rounding.  d_nll, d_grad (may be null) receive the NLL and
+ * gradient at that theta.  Any other evaluation on the context (pwa_nll,
+ * pwa_grad, pwa_partials, pwa_fit, pwa_hessian, pwa_fit_fractions, pwa_bind)
+ * ends the reuse: PWA_E_STATE until the next pwa_hvp.  Uses the current
+ * precision (a full pass if the cached totals are of the other one).
+ * Errors: PWA_E_INVALID, PWA_E_STATE, PWA_E_HIP. */
+int pwa_hvp_reuse(pwa_ctx* ctx, const double* d_v, double* d_hv, double* d_nll, double* d_grad,
+                  hipStream_t stream);
+
 /* Per-event intensity omega(x) = |sum_k c_k a_k(x)|^2 of eq. (1) at theta
  * for the bound data events (which = 0; n_data outputs) or MC events
  * (which = 1; n_mc outputs), in the event order given to pwa_bind, using the

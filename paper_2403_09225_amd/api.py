@@ -147,6 +147,17 @@ class Likelihood:
             ctypes.c_void_p(base), ctypes.c_void_p(base + 8), _stream()))
         return out[1 + self.n_par:], out[0], out[1:1 + self.n_par]
 
+    def hvp_reuse(self, v):
+        """H v at the theta of the last hvp() call (direction-only pass);
+        returns (hv, nll, grad) like hvp()."""
+        vv = self._theta(v)
+        out = torch.empty(1 + 2 * self.n_par, dtype=torch.float64, device=self.device)
+        base = out.data_ptr()
+        L.check("pwa_hvp_reuse", self.lib.pwa_hvp_reuse(
+            self._h, _ptr(vv), ctypes.c_void_p(base + 8 * (1 + self.n_par)),
+            ctypes.c_void_p(base), ctypes.c_void_p(base + 8), _stream()))
+        return out[1 + self.n_par:], out[0], out[1:1 + self.n_par]
+
     def intensity(self, theta, which="data"):
         """Per-event omega(x) at theta for the bound data or MC events (eq. (1))."""
         t = self._theta(theta)

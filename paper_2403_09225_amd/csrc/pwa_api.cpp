@@ -35,6 +35,10 @@ struct pwa_ctx {
   double* tot = nullptr;
   double* dd = nullptr;
   double* scratch = nullptr;
+  // Direction-independent totals of the last full HVP pass (in `tot`) and
+  // its theta (a copy in scratch) may serve further HVPs at that theta.
+  bool hvp_cache = false;
+  int cache_prec = 0;
   double* planes64 = nullptr;
   float* planes32 = nullptr;
   int cu_count = 0;
@@ -191,12 +195,24 @@ int fold_timing(pwa_ctx* c) {
   return PWA_OK;
 }
 
+static double* cache_theta_slot(pwa_ctx* c) { return c->scratch + 7 * c->P; }
+
 // One evaluation: table, pass, reduction and finaliser.  With mc_only the
 // grid covers the MC events alone (the data sums come out as zero).
+// MODE_HVPB (an HVP at the theta of the last full HVP pass, which d_theta
+// must equal) runs as a full HVP pass when no such totals are cached for
+// this precision or the launch shape is not a wave-group shape.
 int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta,
              const double* d_v, double* d_nll, double* d_grad, double* d_hv, double* d_dd,
              hipStream_t st, bool mc_only = false) {
   int L = 2, T = 1, R = 1;
+  if (mode == MODE_HVPB) {
+    shape_of(c, mode, L, T, R);
+    if (!(c->hvp_cache && c->cache_prec == prec && L == 2 && out_kind == OUT_COMBINED && !mc_only))
+      mode = MODE_HVP;
+  }
+  const bool reuse = (mode == MODE_HVPB);
+  c->hvp_cache = false;   // every pass rewrites the totals; set again below
   shape_of(c, mode, L, T, R);
   const int kslots = T * R;
   hipError_t e = launch_table(d_theta, d_v, c->md, kslots, c->tbl64, c->tbl32, c->itbl, c->status, st);
@@ -233,7 +249,7 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
   f.tot = c->tot;
   f.nb_data = a.nb_data;
   f.nb_mc = a.nb_mc;
-  f.V = 1 + (mode == MODE_HVP ? NMOM_HVP : (mode == MODE_GRAD ? NMOM_GRAD : 0)) * c->K;
+  f.V = 1 + (mode == MODE_HVP ? NMOM_HVP : (mode == MODE_NLL ? 0 : NMOM_GRAD)) * c->K;
   f.tbl = c->tbl64;
   f.K = c->K;
   f.mode = mode;
@@ -247,7 +263,18 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
   f.dd_out = d_dd;
   f.status = c->status;
   e = launch_final(f, st);
-  return e == hipSuccess ? PWA_OK : PWA_E_HIP;
+  if (e != hipSuccess) return PWA_E_HIP;
+  if (mode == MODE_HVP && out_kind == OUT_COMBINED && !mc_only) {
+    double* ct = cache_theta_slot(c);
+    if (d_theta != ct &&
+        hipMemcpyAsync(ct, d_theta, sizeof(double) * c->P, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return PWA_E_HIP;
+    c->hvp_cache = true;
+    c->cache_prec = prec;
+  } else if (reuse) {
+    c->hvp_cache = true;
+  }
+  return PWA_OK;
 }
 
 int check_prec(const pwa_ctx* c, int prec) {
@@ -390,6 +417,7 @@ int pwa_bind(pwa_ctx* c, const double* d_s12, const double* d_s13, int64_t n_dat
       return PWA_E_HIP;
   }
   c->bound = true;
+  c->hvp_cache = false;
   return PWA_OK;
 }
 
@@ -465,6 +493,15 @@ int pwa_hvp(pwa_ctx* c, const double* d_theta, const double* d_v, double* d_hv, 
   if (!c->bound) return PWA_E_STATE;
   return run_eval(c, MODE_HVP, OUT_COMBINED, c->precision, d_theta, d_v, d_nll, d_grad, d_hv,
                   nullptr, st);
+}
+
+int pwa_hvp_reuse(pwa_ctx* c, const double* d_v, double* d_hv, double* d_nll, double* d_grad,
+                  hipStream_t st) {
+  if (!c || !d_v || !d_hv) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  if (!c->hvp_cache) return PWA_E_STATE;
+  return run_eval(c, MODE_HVPB, OUT_COMBINED, c->precision, cache_theta_slot(c), d_v, d_nll,
+                  d_grad, d_hv, nullptr, st);
 }
 
 int pwa_intensity(pwa_ctx* c, const double* d_theta, int32_t which, double* d_out,
@@ -572,7 +609,9 @@ struct Fitter {
            std::vector<double>& hp) {
     (void)x_on_device_dummy;
     if (!up(p, d_v)) return false;
-    if (run_eval(c, MODE_HVP, OUT_COMBINED, prec_hvp, d_x, d_v, nullptr, nullptr,
+    // d_x holds the Newton iterate for the whole CG solve: after the first
+    // (full) pass, the direction-only pass reuses its theta-only totals
+    if (run_eval(c, MODE_HVPB, OUT_COMBINED, prec_hvp, d_x, d_v, nullptr, nullptr,
                  d_out + 1 + P, nullptr, st) != PWA_OK) {
       err = PWA_E_HIP;
       return false;
@@ -943,10 +982,11 @@ int pwa_hessian(pwa_ctx* c, const double* d_theta, double* d_H, hipStream_t st) 
   if (!c->bound) return PWA_E_STATE;
   const int P = c->P;
   double* d_e = unit_slot(c);
+  c->hvp_cache = false;   // the first column is a full pass at d_theta
   for (int j = 0; j < P; ++j) {
     if (launch_unit(d_e, P, j, st) != hipSuccess) return PWA_E_HIP;
-    const int r = run_eval(c, MODE_HVP, OUT_COMBINED, c->precision, d_theta, d_e, nullptr, nullptr,
-                           d_H + (size_t)j * P, nullptr, st);
+    const int r = run_eval(c, MODE_HVPB, OUT_COMBINED, c->precision, d_theta, d_e, nullptr,
+                           nullptr, d_H + (size_t)j * P, nullptr, st);
     if (r != PWA_OK) return r;
   }
   return launch_symmetrise(d_H, P, st) == hipSuccess ? PWA_OK : PWA_E_HIP;

@@ -64,7 +64,10 @@ constexpr int BLOCK = 256;    // threads per block of the evaluation kernels
 constexpr int MAX_BLOCKS = 4096;
 
 // Evaluation modes.
-enum Mode : int { MODE_NLL = 0, MODE_GRAD = 1, MODE_HVP = 2 };
+// MODE_HVPB: a Hessian-vector product at the theta of the previous full
+// HVP pass; the pass accumulates the direction moments B1..B3 only and the
+// finaliser reuses that pass's theta-only totals (S, C1..C6).
+enum Mode : int { MODE_NLL = 0, MODE_GRAD = 1, MODE_HVP = 2, MODE_HVPB = 3 };
 
 // Output kinds of the finaliser.
 enum OutKind : int { OUT_COMBINED = 0, OUT_PARTIALS = 1 };

@@ -638,10 +638,12 @@ template <typename Real, int MODE, int G, int R>
 __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
   typedef typename CPtr<Real>::type CReal;
   constexpr bool HVP = (MODE == MODE_HVP);
+  constexpr bool BON = (MODE == MODE_HVPB);   // direction moments B1..B3 only
+  constexpr bool ZD = HVP || BON;             // zdot needed
   constexpr bool DER = (MODE != MODE_NLL);
-  constexpr int NM = HVP ? NMOM_HVP : (DER ? NMOM_GRAD : 0);
+  constexpr int NM = HVP ? NMOM_HVP : (DER ? NMOM_GRAD : 0);   // B-only: 6, as GRAD
   constexpr int NA = NM * R;
-  constexpr int NX = HVP ? 4 : 2;     // exchanged reals per lane: z (, zdot)
+  constexpr int NX = ZD ? 4 : 2;      // exchanged reals per lane: z (, zdot)
 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -744,7 +746,7 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
         const Real uwr = u * wr, uwi = u * wi;
         zr = fma_r(t[TB_CBR], uwr, fma_r(-t[TB_CBI], uwi, zr));
         zi = fma_r(t[TB_CBR], uwi, fma_r(t[TB_CBI], uwr, zi));
-        if constexpr (HVP) {
+        if constexpr (ZD) {
           const Real uw2r = uwr * wr - uwi * wi, uw2i = uwr * wi + uwi * wr;
           const Real kr = mad_nc(t[TB_K3R], g, t[TB_K2R]);
           const Real ki = mad_nc(t[TB_K3I], g, t[TB_K2I]);
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
       if constexpr (G > 1) {
         xch[buf][wv][0][lane][0] = zr;
         xch[buf][wv][0][lane][1] = zi;
-        if constexpr (HVP) {
+        if constexpr (ZD) {
           xch[buf][wv][1][lane][0] = zdr;
           xch[buf][wv][1][lane][1] = zdi;
         }
@@ -769,7 +771,7 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
         for (int g = 0; g < G; ++g) {
           zr += xch[buf][g][0][lane][0];
           zi += xch[buf][g][0][lane][1];
-          if constexpr (HVP) {
+          if constexpr (ZD) {
             zdr += xch[buf][g][1][lane][0];
             zdi += xch[buf][g][1][lane][1];
           }
@@ -781,19 +783,19 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
       Real gr = 0, gi = 0, alr = 0, ali = 0;
       double sterm = 0.0;
       if (rg.is_data) {
-        if (wv == 0) sterm = (double)log_r(om);
+        if (!BON && wv == 0) sterm = (double)log_r(om);
         if constexpr (DER) {
           const Real io = rcp_r(om);
           gr = zr * io;
           gi = -zi * io;
-          if constexpr (HVP) {
+          if constexpr (ZD) {
             const Real t = 2 * (zr * zdr + zi * zdi) * io;
             alr = (zdr - t * zr) * io;
             ali = (t * zi - zdi) * io;
           }
         }
       } else {
-        sterm = (double)om;
+        if (!BON) sterm = (double)om;
         gr = zr;
         gi = -zi;
         alr = zdr;
@@ -806,7 +808,24 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
       if (wv == 0) accS += sterm;
 
       // ---- pass 2: moments (chain p = x u w, q = p w, r = q w)
-      if constexpr (DER) {
+      if constexpr (BON) {
+        // B1..B3 = alpha u {w, w^2, g w^2}: the only moments that depend on
+        // the direction v (C1..C6 depend on theta alone)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const Real wr = cwr[r], wi = cwi[r], g = gc[r];
+          const Real uwr = cu[r] * wr, uwi = cu[r] * wi;
+          double* m = acc + NM * r;
+          const Real ar_ = alr * uwr - ali * uwi, ai_ = alr * uwi + ali * uwr;
+          const Real br_ = ar_ * wr - ai_ * wi, bi_ = ar_ * wi + ai_ * wr;
+          acc_add(m[0], ar_);
+          acc_add(m[1], ai_);
+          acc_add(m[2], br_);
+          acc_add(m[3], bi_);
+          acc_fma(m[4], g, br_);
+          acc_fma(m[5], g, bi_);
+        }
+      } else if constexpr (DER) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const Real wr = cwr[r], wi = cwi[r], g = gc[r];
@@ -986,8 +1005,17 @@ __global__ __launch_bounds__(1024) void reduce_kernel(FinalArgs f) {
   __syncthreads();
   if (grp == 0 && vv < 2 * f.V) {
     for (int g = 1; g < 16; ++g) dd_add(hi, lo, red[g][lane][0], red[g][lane][1]);
-    f.tot[2 * vv] = hi;
-    f.tot[2 * vv + 1] = lo;
+    int dst = vv;
+    if (f.mode == MODE_HVPB) {
+      // direction moments into their slots of the full HVP totals; the
+      // theta-only values (S, C1..C6) there stay those of the last full pass
+      const int set = vv >= f.V, vi = vv - set * f.V;
+      if (vi == 0) return;
+      const int k = (vi - 1) / NMOM_GRAD, i = (vi - 1) % NMOM_GRAD;
+      dst = set * (1 + NMOM_HVP * f.K) + 1 + NMOM_HVP * k + NMOM_GRAD + i;
+    }
+    f.tot[2 * dst] = hi;
+    f.tot[2 * dst + 1] = lo;
   }
 }
 
@@ -1201,6 +1229,8 @@ static EvalFn wg_fn(int is_f32, int mode, int G, int R) {
       return is_f32 ? wg_kernel<float, MODE_NLL, GG, RR> : wg_kernel<double, MODE_NLL, GG, RR>;   \
     if (mode == MODE_GRAD)                                                            \
       return is_f32 ? wg_kernel<float, MODE_GRAD, GG, RR> : wg_kernel<double, MODE_GRAD, GG, RR>; \
+    if (mode == MODE_HVPB)                                                            \
+      return is_f32 ? wg_kernel<float, MODE_HVPB, GG, RR> : wg_kernel<double, MODE_HVPB, GG, RR>; \
     return is_f32 ? wg_kernel<float, MODE_HVP, GG, RR> : wg_kernel<double, MODE_HVP, GG, RR>;     \
   }
   PWA_WG_SHAPES(PWA_PICK)
@@ -1212,6 +1242,7 @@ static EvalFn wg_fn(int is_f32, int mode, int G, int R) {
 // layout 2: wave group (G waves per 64 events, 64 G-thread blocks).
 static EvalFn pick_fn(int is_f32, int mode, int layout, int T, int R) {
   if (layout == 2) return wg_fn(is_f32, mode, T, R);
+  if (mode == MODE_HVPB) return nullptr;   // wave-group layout only
   if (mode == MODE_NLL && T == 1 && nll_shape_built(R)) return nll_fn(is_f32, R);
   return eval_fn(is_f32, mode, T, R);
 }
@@ -1239,7 +1270,13 @@ hipError_t launch_final(const FinalArgs& f, hipStream_t st) {
   hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(1024), 0, st, f);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(final_kernel, dim3(1), dim3(1024), 0, st, f);
+  // a direction-only pass completes the full HVP totals: contract those
+  FinalArgs g = f;
+  if (f.mode == MODE_HVPB) {
+    g.mode = MODE_HVP;
+    g.V = 1 + NMOM_HVP * f.K;
+  }
+  hipLaunchKernelGGL(final_kernel, dim3(1), dim3(1024), 0, st, g);
   return hipGetLastError();
 }
 

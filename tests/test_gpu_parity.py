@@ -228,3 +228,68 @@ def test_many_iterations_per_block():
     model, th, data, mc, v = case(12, 40_000, 190_000, 140)
     lik = likelihood(model, data, mc)
     _check_fp64(lik, model, th, data, mc, v)
+
+
+# ------------------------------------------------- HVP reuse at a fixed theta
+@pytest.mark.parametrize("K,nd,nm,seed,shape", [
+    (1, 777, 3001, 60, None), (2, 2011, 9013, 61, None), (5, 1500, 6007, 62, None),
+    (12, 3001, 12007, 63, None), (17, 1201, 4999, 64, None), (30, 1003, 4001, 65, None),
+    (12, 1999, 7001, 66, (2, 3, 4)), (16, 913, 3007, 67, (1, 16, 2)), (40, 501, 2001, 68, None)])
+def test_hvp_reuse_parity(K, nd, nm, seed, shape):
+    """pwa_hvp_reuse (direction moments only, theta-only totals of the last
+    pwa_hvp) against the oracle for several new directions, FP64 and FP32
+    streams, and equal to a full pass to rounding.  Layout-1 shapes and
+    K > 32 take the full pass inside pwa_hvp_reuse."""
+    say(f"[hvp reuse] K={K} shape={shape}")
+    model, th, data, mc, v = case(K, nd, nm, seed)
+    lik = likelihood(model, data, mc, streams=("f64", "f32"))
+    if shape:
+        lik.set_launch_shape(*shape)
+    f, g, _, S, _ = oracle_all(model, data, mc, th, v)
+    # FP32 stream: 3e-5 of the absolute-sum scale up to K = 32; with more
+    # resonances z sums more FP32-rounded terms that cancel, and the bound
+    # is widened to 1e-4 (the FP64 bound does not change)
+    tol32 = 3e-5 if K <= 32 else 1e-4
+    for prec, tol in (("f64", 1e-10), ("f32", tol32)):
+        lik.set_precision(prec)
+        lik.hvp(th, v)
+        for d in range(3):
+            w = rng(seed * 10 + d).normal(size=4 * K)
+            _, _, hvo = oracle.hvp(data, mc, model, th, w)
+            Sw, SHw = oracle.grad_scale(data, mc, model, th, v=w)
+            hv, nll, gg = lik.hvp_reuse(w)
+            assert abs(float(nll) - f) <= (1e-10 if prec == "f64" else 1e-5) * abs(f)
+            assert_close(f"grad reuse {prec}", _np(gg), g, S, tol)
+            assert_close(f"hv reuse {prec} dir {d}", _np(hv), hvo, SHw + Sw + np.abs(hvo), tol)
+            full, _, _ = lik.hvp(th, w)
+            scale = SHw + Sw + np.abs(hvo)
+            assert np.all(np.abs(_np(hv) - _np(full)) <= (1e-12 if prec == "f64" else 1e-6) * scale)
+
+
+def test_hvp_reuse_state():
+    """Reuse needs the totals of a pwa_hvp on this context: before any, and
+    after any other evaluation, it is refused; a precision change makes it
+    take a full pass at the cached theta (still the right product)."""
+    from paper_2403_09225_amd import _lib as L
+    model, th, data, mc, v = case(6, 1001, 4001, 70)
+    lik = likelihood(model, data, mc, streams=("f64", "f32"))
+    w = rng(71).normal(size=24)
+    with pytest.raises(L.PwaError):
+        lik.hvp_reuse(w)
+    ref, _, _ = lik.hvp(th, w)
+    lik.hvp(th, v)
+    hv, _, _ = lik.hvp_reuse(w)
+    torch.testing.assert_close(hv, ref, rtol=1e-10, atol=1e-10 * float(ref.abs().max()))
+    lik.nll(th)
+    with pytest.raises(L.PwaError):
+        lik.hvp_reuse(w)
+    lik.hvp(th, v)
+    lik.set_precision("f32")
+    hv32, _, _ = lik.hvp_reuse(w)
+    ref32, _, _ = lik.hvp(th, w)
+    torch.testing.assert_close(hv32, ref32, rtol=1e-6, atol=1e-6 * float(ref32.abs().max()))
+    lik.set_precision("f64")
+    lik.hvp(th, v)
+    lik.grad(th + 0.01)
+    with pytest.raises(L.PwaError):
+        lik.hvp_reuse(w)
