@@ -213,6 +213,13 @@ typedef struct pwa_fit_opts {
                              stays 1/2 and Newton-CG converges linearly);
                              1 = relative eta = min(1/2, sqrt(sum |g| /
                              sum |g_0|)), superlinear (Eisenstat-Walker)   */
+  int32_t precondition;   /* 0: plain CG (scipy's Newton-CG); 1: CG
+                             preconditioned with the inverse of |H| (H from
+                             HVPs along the free unit vectors at the first
+                             iterate, eigenvalues floored at 1e-6 of the
+                             largest), rebuilt when a solve needs more than
+                             max(8, P/4) CG steps; those HVPs are counted
+                             in n_hvp                                     */
 } pwa_fit_opts;
 
 /* Fit report (host memory, written by pwa_fit). */

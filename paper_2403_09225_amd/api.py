@@ -246,10 +246,11 @@ class Likelihood:
 
     # ------------------------------------------------------------------- fit
     def fit(self, theta0, xtol=1e-8, maxiter=200, cg_maxiter=0, time_cap_s=0.0,
-            hvp_precision="f64", free_mask=None, forcing="scipy"):
+            hvp_precision="f64", free_mask=None, forcing="scipy", precondition=False):
         """Newton-CG fit from theta0; returns (theta, report dict).
         forcing: "scipy" (eta = min(1/2, sqrt(sum|g|))) or "relative"
-        (eta = min(1/2, sqrt(sum|g| / sum|g_0|)))."""
+        (eta = min(1/2, sqrt(sum|g| / sum|g_0|))).  precondition: CG with
+        the inverse of |H| built from HVPs (see pwa_fit_opts)."""
         t = self._theta(theta0).clone()
         o = L.PwaFitOpts()
         o.xtol = xtol
@@ -258,6 +259,7 @@ class Likelihood:
         o.time_cap_s = time_cap_s
         o.hvp_precision = L.PWA_PREC_F32 if hvp_precision == "f32" else L.PWA_PREC_F64
         o.forcing = {"scipy": 0, "relative": 1}[forcing]
+        o.precondition = 1 if precondition else 0
         o.free_mask_set = 0 if free_mask is None else 1
         if free_mask is not None:
             for i, f in enumerate(free_mask):

@@ -730,12 +730,113 @@ bool wolfe(Fitter& F, const std::vector<double>& x, double f0, const std::vector
 // Forcing term below which a mixed-precision fit takes its HVPs in FP64.
 constexpr double kMixedEtaSwitch = 1e-3;
 
+// Eigen-decomposition of a symmetric n x n matrix A (row-major, destroyed)
+// by cyclic Jacobi rotations: A = V diag(w) V^T, V row-major with the
+// eigenvectors as columns.
+void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i) {
+      diag += A[(size_t)i * n + i] * A[(size_t)i * n + i];
+      for (int j = i + 1; j < n; ++j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+    }
+    if (off <= 1e-30 * diag || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (apq == 0.0) continue;
+        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = cs * akp - sn * akq;
+          A[(size_t)k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = cs * apk - sn * aqk;
+          A[(size_t)q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+          V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
+// CG preconditioner from the Hessian at the current iterate: the inverse of
+// its absolute-value form V |diag(w)| V^T on the free parameters, with
+// eigenvalues below 1e-6 of the largest raised to that floor (the coupling
+// phase and scale directions are null directions of H).  P HVPs along the
+// unit vectors of the free parameters.
+bool build_preconditioner(Fitter& F, const std::vector<double>& x, std::vector<int>& fidx,
+                          std::vector<double>& Minv) {
+  const int P = F.P;
+  fidx.clear();
+  for (int i = 0; i < P; ++i)
+    if (F.free_[i]) fidx.push_back(i);
+  const int n = (int)fidx.size();
+  std::vector<double> H((size_t)n * n), e(P, 0.0), col;
+  for (int j = 0; j < n; ++j) {
+    e[fidx[j]] = 1.0;
+    if (!F.hvp(x, e, col)) return false;
+    e[fidx[j]] = 0.0;
+    for (int i = 0; i < n; ++i) H[(size_t)i * n + j] = col[fidx[i]];
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = i + 1; j < n; ++j) {
+      const double m = 0.5 * (H[(size_t)i * n + j] + H[(size_t)j * n + i]);
+      H[(size_t)i * n + j] = H[(size_t)j * n + i] = m;
+    }
+  std::vector<double> w, V;
+  jacobi_eigen(n, H, w, V);
+  double wmax = 0.0;
+  for (double v : w) wmax = std::max(wmax, fabs(v));
+  if (!(wmax > 0.0) || !isfinite(wmax)) return false;
+  const double floor_ = 1e-6 * wmax;
+  Minv.assign((size_t)n * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    const double s = 1.0 / std::max(fabs(w[k]), floor_);
+    for (int i = 0; i < n; ++i) {
+      const double vik = V[(size_t)i * n + k] * s;
+      for (int j = 0; j < n; ++j) Minv[(size_t)i * n + j] += vik * V[(size_t)j * n + k];
+    }
+  }
+  return true;
+}
+
+// z = Minv r on the free parameters (zero elsewhere); identity without a
+// preconditioner.
+void apply_preconditioner(const std::vector<int>& fidx, const std::vector<double>& Minv,
+                          const std::vector<double>& r, std::vector<double>& z) {
+  z.assign(r.size(), 0.0);
+  if (Minv.empty()) {
+    z = r;
+    return;
+  }
+  const int n = (int)fidx.size();
+  for (int i = 0; i < n; ++i) {
+    double a = 0.0;
+    for (int j = 0; j < n; ++j) a += Minv[(size_t)i * n + j] * r[fidx[j]];
+    z[fidx[i]] = a;
+  }
+}
+
 int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* rep,
             hipStream_t st) {
   if (!c || !d_theta || !o) return PWA_E_INVALID;
   if (!c->bound) return PWA_E_STATE;
   if (!(o->xtol > 0.0) || !isfinite(o->xtol)) return PWA_E_INVALID;
   if (o->forcing != 0 && o->forcing != 1) return PWA_E_INVALID;
+  if (o->precondition != 0 && o->precondition != 1) return PWA_E_INVALID;
   const int hp = o->hvp_precision;
   if (check_prec(c, hp) != PWA_OK) return PWA_E_INVALID;
   const auto t0 = std::chrono::steady_clock::now();
@@ -768,7 +869,11 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
   if (!isfinite(f)) status = PWA_E_DOMAIN;
   best_x = x;
   double best_f = f;
-  std::vector<double> r(P), pcg(P), xs(P), Ap, x1, g1;
+  std::vector<double> r(P), pcg(P), xs(P), zc(P), Ap, x1, g1;
+  // preconditioner state: free indices, inverse, CG steps of the last solve
+  std::vector<int> fidx;
+  std::vector<double> Minv;
+  int last_cg = 0;
   while (status == PWA_OK) {
     if (it >= maxiter) { status = PWA_E_NOCONV; break; }
     if (o->time_cap_s > 0 && elapsed() > o->time_cap_s) { status = PWA_E_NOCONV; break; }
@@ -782,19 +887,30 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
     // them; Newton steps whose forcing term asks for more use FP64 HVPs.
     F.prec_hvp = (hp == PWA_PREC_F32 && eta < kMixedEtaSwitch) ? PWA_PREC_F64 : hp;
     std::fill(xs.begin(), xs.end(), 0.0);
-    r = g;
-    for (int i = 0; i < P; ++i) pcg[i] = -g[i];
-    double dri0 = dot(r, r);
     // the HVPs are taken at x: upload x once
     if (!F.up(x, F.d_x)) return F.err;
-    for (int k = 0, i = 0; k < cg_max; ++k) {
+    // Optional preconditioner: the Hessian at the first iterate, rebuilt
+    // when the previous solve needed many CG steps (it has gone stale).
+    if (o->precondition == 1 && (Minv.empty() || last_cg > std::max(8, P / 4))) {
+      if (!build_preconditioner(F, x, fidx, Minv)) {
+        if (F.err != PWA_OK) return F.err;
+        Minv.clear();
+      }
+    }
+    r = g;
+    apply_preconditioner(fidx, Minv, r, zc);
+    for (int i = 0; i < P; ++i) pcg[i] = -zc[i];
+    double dri0 = dot(r, zc);
+    int i = 0;
+    for (int k = 0; k < cg_max; ++k) {
       if (sum_abs(r) <= termcond) break;
       if (!F.hvp(x, pcg, Ap)) return F.err;
       const double curv = dot(pcg, Ap);
       if (0.0 <= curv && curv <= 3.0 * 2.220446049250313e-16) break;
       if (curv < 0.0) {
         if (i > 0) break;
-        for (int j = 0; j < P; ++j) xs[j] = dri0 / (-curv) * (-g[j]);
+        // first direction: step along the (preconditioned) steepest descent
+        for (int j = 0; j < P; ++j) xs[j] = dri0 / (-curv) * pcg[j];
         break;
       }
       const double al = dri0 / curv;
@@ -802,12 +918,14 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
         xs[j] += al * pcg[j];
         r[j] += al * Ap[j];
       }
-      const double dri1 = dot(r, r);
+      apply_preconditioner(fidx, Minv, r, zc);
+      const double dri1 = dot(r, zc);
       const double be = dri1 / dri0;
-      for (int j = 0; j < P; ++j) pcg[j] = -r[j] + be * pcg[j];
+      for (int j = 0; j < P; ++j) pcg[j] = -zc[j] + be * pcg[j];
       ++i;
       dri0 = dri1;
     }
+    last_cg = i;
     // A Newton step already within the tolerance ends the fit here: at the
     // minimum the NLL is flat to rounding, and a line search along such a
     // step can find no decrease.
