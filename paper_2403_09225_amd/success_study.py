@@ -30,7 +30,8 @@ from .toys import ToyGenerator, uniform_dalitz
 
 
 def run(K=6, n_events=10_000, n_mc=1_000_000, n_starts=300, xtols=(1e-5, 1e-8), time_cap_s=10.0,
-        maxiter=1000, forcing="scipy", tol=1.0, seed=0, log_every=0, device="cuda"):
+        maxiter=1000, forcing="scipy", tol=1.0, seed=0, log_every=0, device="cuda",
+        precondition=False):
     """Run the study; returns (summary dict, per-fit rows dict of arrays)."""
     ch, sp = resonance_layout(K)
     prior = Prior.wide(ch)
@@ -57,7 +58,7 @@ def run(K=6, n_events=10_000, n_mc=1_000_000, n_starts=300, xtols=(1e-5, 1e-8), 
         conv = np.empty(n_starts, dtype=np.int64)
         for i in range(n_starts):
             _, rep = lik.fit(starts[i], xtol=xt, maxiter=maxiter, time_cap_s=time_cap_s,
-                             forcing=forcing)
+                             forcing=forcing, precondition=precondition)
             nll[i], sec[i], it[i] = rep["nll"], rep["seconds"], rep["iterations"]
             hvp[i], code[i], conv[i] = rep["n_hvp"], rep["code"], rep["converged"]
             if log_every and (i + 1) % log_every == 0:
@@ -68,7 +69,8 @@ def run(K=6, n_events=10_000, n_mc=1_000_000, n_starts=300, xtols=(1e-5, 1e-8), 
     finite = [r["nll"][np.isfinite(r["nll"])] for k, r in rows.items() if k != "start"]
     nll_min = float(min([nll_truth_fit] + [float(f.min()) for f in finite if f.size]))
     summary = {"K": K, "n_par": 4 * K, "n_events": n_events, "n_mc": n_mc, "n_starts": n_starts,
-               "time_cap_s": time_cap_s, "forcing": forcing, "tol": tol, "seed": seed,
+               "time_cap_s": time_cap_s, "forcing": forcing, "precondition": bool(precondition),
+               "tol": tol, "seed": seed,
                "nll_min": nll_min, "nll_truth_fit": nll_truth_fit,
                "truth_fit_is_global": bool(nll_truth_fit <= nll_min + tol)}
     for key, r in rows.items():
@@ -106,12 +108,14 @@ def main(argv=None):
     ap.add_argument("--xtol", type=float, nargs="+", default=[1e-5, 1e-8])
     ap.add_argument("--time-cap", type=float, default=10.0)
     ap.add_argument("--forcing", choices=["scipy", "relative"], default="scipy")
+    ap.add_argument("--precondition", action="store_true",
+                    help="CG preconditioned with |H|^-1 (pwa_fit_opts.precondition)")
     ap.add_argument("--tol", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default="")
     a = ap.parse_args(argv)
     summary, rows = run(a.K, a.events, a.mc, a.starts, tuple(a.xtol), a.time_cap, forcing=a.forcing,
-                        tol=a.tol, seed=a.seed, log_every=25)
+                        tol=a.tol, seed=a.seed, log_every=25, precondition=a.precondition)
     text = json.dumps(summary)
     print(text, flush=True)
     if a.out:
