@@ -201,16 +201,14 @@ static double* cache_theta_slot(pwa_ctx* c) { return c->scratch + 7 * c->P; }
 // grid covers the MC events alone (the data sums come out as zero).
 // MODE_HVPB (an HVP at the theta of the last full HVP pass, which d_theta
 // must equal) runs as a full HVP pass when no such totals are cached for
-// this precision or the launch shape is not a wave-group shape.
+// this precision.
 int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta,
              const double* d_v, double* d_nll, double* d_grad, double* d_hv, double* d_dd,
              hipStream_t st, bool mc_only = false) {
   int L = 2, T = 1, R = 1;
-  if (mode == MODE_HVPB) {
-    shape_of(c, mode, L, T, R);
-    if (!(c->hvp_cache && c->cache_prec == prec && L == 2 && out_kind == OUT_COMBINED && !mc_only))
-      mode = MODE_HVP;
-  }
+  if (mode == MODE_HVPB &&
+      !(c->hvp_cache && c->cache_prec == prec && out_kind == OUT_COMBINED && !mc_only))
+    mode = MODE_HVP;
   const bool reuse = (mode == MODE_HVPB);
   c->hvp_cache = false;   // every pass rewrites the totals; set again below
   shape_of(c, mode, L, T, R);

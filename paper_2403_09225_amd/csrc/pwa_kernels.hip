@@ -362,6 +362,8 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
   static_assert(64 % T == 0, "team size must divide the wavefront");
   typedef typename CPtr<Real>::type CReal;
   constexpr bool HVP = (MODE == MODE_HVP);
+  constexpr bool BON = (MODE == MODE_HVPB);   // direction moments B1..B3 only
+  constexpr bool ZD = HVP || BON;             // zdot needed
   constexpr bool DER = (MODE != MODE_NLL);
   constexpr int TEAMS = BLOCK / T;
   constexpr int NM = HVP ? NMOM_HVP : (DER ? NMOM_GRAD : 0);
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
         const Real cbr = TB(r, TB_CBR), cbi = TB(r, TB_CBI);
         zr = fma_r(cbr, uwr, fma_r(-cbi, uwi, zr));
         zi = fma_r(cbr, uwi, fma_r(cbi, uwr, zi));
-        if constexpr (HVP) {
+        if constexpr (ZD) {
           // zdot += K1 u w + (K2 + K3 g) u w^2
           const Real uw2r = uwr * wr - uwi * wi, uw2i = uwr * wi + uwi * wr;
           const Real kr = (T == 1) ? mad_nc(TB(r, TB_K3R), g, TB(r, TB_K2R))
@@ -501,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
         for (int off = 1; off < T; off <<= 1) {
           zr += __shfl_xor(zr, off);
           zi += __shfl_xor(zi, off);
-          if constexpr (HVP) {
+          if constexpr (ZD) {
             zdr += __shfl_xor(zdr, off);
             zdi += __shfl_xor(zdi, off);
           }
@@ -511,21 +513,21 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
       // ---- per-event weights
       const Real om = zr * zr + zi * zi;
       Real gr = 0, gi = 0, alr = 0, ali = 0;
-      double sterm;
+      double sterm = 0.0;
       if (rg.is_data) {
-        sterm = (double)log_r(om);
+        if constexpr (!BON) sterm = (double)log_r(om);
         if constexpr (DER) {
           const Real io = rcp_r(om);
           gr = zr * io;
           gi = -zi * io;
-          if constexpr (HVP) {
+          if constexpr (ZD) {
             const Real t = 2 * (zr * zdr + zi * zdi) * io;
             alr = (zdr - t * zr) * io;
             ali = (t * zi - zdi) * io;
           }
         }
       } else {
-        sterm = (double)om;
+        if constexpr (!BON) sterm = (double)om;
         gr = zr;
         gi = -zi;
         alr = zdr;
@@ -539,7 +541,22 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
 
       // ---- pass 2: moments, as the chain p = x u w, q = p w, r = q w
       // (x = gamma or alpha) so that C2 = sum q, C3 = sum g q, C4 = sum r, ...
-      if constexpr (DER) {
+      if constexpr (BON) {
+        // B1..B3 = alpha u {w, w^2, g w^2} only (C1..C6 depend on theta alone)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const Real wr = cwr[r], wi = cwi[r], uwr = cuwr[r], uwi = cuwi[r], g = gc[r];
+          double* m = acc + NM * r;
+          const Real ar_ = alr * uwr - ali * uwi, ai_ = alr * uwi + ali * uwr;
+          const Real br_ = ar_ * wr - ai_ * wi, bi_ = ar_ * wi + ai_ * wr;
+          acc_add(m[0], ar_);
+          acc_add(m[1], ai_);
+          acc_add(m[2], br_);
+          acc_add(m[3], bi_);
+          acc_fma(m[4], g, br_);
+          acc_fma(m[5], g, bi_);
+        }
+      } else if constexpr (DER) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const Real wr = cwr[r], wi = cwi[r], uwr = cuwr[r], uwi = cuwi[r], g = gc[r];
@@ -1196,6 +1213,8 @@ static EvalFn eval_fn(int is_f32, int mode, int T, int R) {
       return is_f32 ? eval_kernel<float, MODE_NLL, TT, RR> : eval_kernel<double, MODE_NLL, TT, RR>;   \
     if (mode == MODE_GRAD)                                                            \
       return is_f32 ? eval_kernel<float, MODE_GRAD, TT, RR> : eval_kernel<double, MODE_GRAD, TT, RR>; \
+    if (mode == MODE_HVPB)                                                            \
+      return is_f32 ? eval_kernel<float, MODE_HVPB, TT, RR> : eval_kernel<double, MODE_HVPB, TT, RR>; \
     return is_f32 ? eval_kernel<float, MODE_HVP, TT, RR> : eval_kernel<double, MODE_HVP, TT, RR>;     \
   }
   PWA_SHAPES(PWA_PICK)
@@ -1242,7 +1261,6 @@ static EvalFn wg_fn(int is_f32, int mode, int G, int R) {
 // layout 2: wave group (G waves per 64 events, 64 G-thread blocks).
 static EvalFn pick_fn(int is_f32, int mode, int layout, int T, int R) {
   if (layout == 2) return wg_fn(is_f32, mode, T, R);
-  if (mode == MODE_HVPB) return nullptr;   // wave-group layout only
   if (mode == MODE_NLL && T == 1 && nll_shape_built(R)) return nll_fn(is_f32, R);
   return eval_fn(is_f32, mode, T, R);
 }

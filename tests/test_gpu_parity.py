@@ -238,8 +238,8 @@ def test_many_iterations_per_block():
 def test_hvp_reuse_parity(K, nd, nm, seed, shape):
     """pwa_hvp_reuse (direction moments only, theta-only totals of the last
     pwa_hvp) against the oracle for several new directions, FP64 and FP32
-    streams, and equal to a full pass to rounding.  Layout-1 shapes and
-    K > 32 take the full pass inside pwa_hvp_reuse."""
+    streams, and equal to a full pass to rounding, in both layouts (team
+    layout: K > 32 and the (1, 16, 2) case)."""
     say(f"[hvp reuse] K={K} shape={shape}")
     model, th, data, mc, v = case(K, nd, nm, seed)
     lik = likelihood(model, data, mc, streams=("f64", "f32"))
