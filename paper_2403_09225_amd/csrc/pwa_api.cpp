@@ -1105,6 +1105,7 @@ int pwa_hessian(pwa_ctx* c, const double* d_theta, double* d_H, hipStream_t st) 
                            nullptr, d_H + (size_t)j * P, nullptr, st);
     if (r != PWA_OK) return r;
   }
+  c->hvp_cache = false;   // as documented: only pwa_hvp starts a reuse
   return launch_symmetrise(d_H, P, st) == hipSuccess ? PWA_OK : PWA_E_HIP;
 }
 

@@ -293,3 +293,7 @@ def test_hvp_reuse_state():
     lik.grad(th + 0.01)
     with pytest.raises(L.PwaError):
         lik.hvp_reuse(w)
+    lik.hvp(th, v)
+    lik.hessian(th)
+    with pytest.raises(L.PwaError):
+        lik.hvp_reuse(w)
