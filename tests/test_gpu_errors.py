@@ -191,3 +191,33 @@ def test_fullsize_fit_fractions(cfg1):
     Fm = _np(lik.fit_fractions(th - h * d, with_grad=False))
     np.testing.assert_allclose((Fp - Fm) / (2 * h), dF @ d, rtol=1e-5,
                                atol=1e-7 * np.max(np.abs(dF @ d)))
+
+
+def test_fp32_stream_hessian_and_fractions():
+    """The same entry points on the FP32 event stream: Hessian entries to
+    1e-4 of their scale, fractions to 1e-5 relative.  (Random directions
+    meet 3e-5; a unit direction along a mass or width isolates the second
+    derivatives, which carry w^3 terms and so three times the FP32 relative
+    rounding of w = 1/D near a pole, with no averaging over components.)"""
+    model, th, data, mc, _ = case(6, 1999, 7001, 80)
+    lik = likelihood(model, data, mc, streams=("f64", "f32"))
+    lik.set_precision("f32")
+    H = _np(lik.hessian(th))
+    F, dF = lik.fit_fractions(th)
+    P = 24
+    Ho = np.empty((P, P))
+    Sc = np.empty((P, P))
+    for j in range(P):
+        e = _unit(P, j)
+        _, _, col = oracle.hvp(data, mc, model, th, e)
+        S, SH = oracle.grad_scale(data, mc, model, th, v=e)
+        Ho[:, j] = col
+        Sc[:, j] = SH + S + np.abs(col)
+    # symmetrised entries mix two passes: bound by the larger of their scales
+    Ho = 0.5 * (Ho + Ho.T)
+    bound = np.maximum(Sc, Sc.T)
+    for j in range(P):
+        assert_close(f"H32[:, {j}]", H[:, j], Ho[:, j], bound[:, j], 1e-4)
+    Fo, dFo = oracle.fit_fractions(mc, model, th)
+    np.testing.assert_allclose(_np(F), Fo, rtol=1e-5)
+    np.testing.assert_allclose(_np(dF), dFo, rtol=1e-4, atol=1e-5 * (1.0 + np.max(np.abs(dFo))))
