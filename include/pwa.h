@@ -273,6 +273,18 @@ int pwa_hessian(pwa_ctx* ctx, const double* d_theta, double* d_H, hipStream_t st
 int pwa_fit_fractions(pwa_ctx* ctx, const double* d_theta, double* d_ff, double* d_dff,
                       hipStream_t stream);
 
+/* Fraction matrix Phi (K x K, row-major, device, caller-owned): Phi[k][k] =
+ * F_k as above, Phi[k][l] = I_kl = sum_MC 2 Re(conj(c_k a_k) c_l a_l) /
+ * sum_MC |z|^2 for k < l (interference), 0 for k > l; all entries add up
+ * to 1.  Computed from the MC Gram matrix sum_MC conj(a_k) a_l at theta's
+ * masses and widths (FP64 matrix cores, FP64 event stream, K <= 24).
+ * d_ws: caller-owned device scratch of pwa_fraction_matrix_workspace_bytes()
+ * bytes, 256-byte aligned.  Errors: PWA_E_INVALID (K > 24, no FP64 stream,
+ * null), PWA_E_STATE, PWA_E_WORKSPACE, PWA_E_HIP. */
+size_t pwa_fraction_matrix_workspace_bytes(const pwa_ctx* ctx);
+int pwa_fraction_matrix(pwa_ctx* ctx, const double* d_theta, void* d_ws, size_t ws_bytes,
+                        double* d_phi, hipStream_t stream);
+
 /* Covariance matrix of the free parameters (host arrays, P x P row-major):
  * the inverse of H restricted to the rows and columns i with h_free[i] != 0
  * (all of them if h_free is null), by a Cholesky factorisation of that

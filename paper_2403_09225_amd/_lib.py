@@ -82,6 +82,8 @@ SIGNATURES = {
     "pwa_hessian": (c_int32, [_P, _P, _P, _P]),
     "pwa_fit_fractions": (c_int32, [_P, _P, _P, _P, _P]),
     "pwa_covariance": (c_int32, [c_int32, _P, _P, _P]),
+    "pwa_fraction_matrix_workspace_bytes": (c_size_t, [_P]),
+    "pwa_fraction_matrix": (c_int32, [_P, _P, _P, c_size_t, _P, _P]),
     "pwa_propagate": (c_int32, [c_int32, c_int32, _P, _P, _P]),
     # include/pwa_mlp.h
     "pwa_hist2d": (c_int32, [_P, _P, _P, c_int32, c_double, ctypes.POINTER(c_double), _P, _P]),

@@ -236,6 +236,21 @@ class Likelihood:
             self._h, _ptr(t), _ptr(ff), _ptr(dff), _stream()))
         return (ff, dff) if with_grad else ff
 
+    def fraction_matrix(self, theta):
+        """K x K matrix: fit fractions on the diagonal, interference terms
+        I_kl above it (k < l), zero below; the entries add up to 1 (K <= 24)."""
+        t = self._theta(theta)
+        nbytes = int(self.lib.pwa_fraction_matrix_workspace_bytes(self._h))
+        if nbytes == 0:
+            raise ValueError("fraction matrix needs K <= 24 and the FP64 event stream")
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-ws.data_ptr()) % 256
+        out = torch.empty((self.n_res, self.n_res), dtype=torch.float64, device=self.device)
+        L.check("pwa_fraction_matrix", self.lib.pwa_fraction_matrix(
+            self._h, _ptr(t), ctypes.c_void_p(ws.data_ptr() + off), nbytes, _ptr(out), _stream()))
+        torch.cuda.current_stream().synchronize()   # ws is released on return
+        return out
+
     def errors(self, theta, free_mask=None):
         """Covariance of the free parameters, parameter errors, fit fractions
         and their propagated errors at theta (normally a fitted minimum).

@@ -16,6 +16,9 @@ hipError_t launch_mask(const double* theta, double* out, int K, int k, hipStream
 // num[k], row k of dnum (may be null) from a masked pass's partial vector.
 hipError_t launch_ff_take(const double* dd, int P, int k, double* num, double* dnum,
                           hipStream_t st);
+// Fraction matrix (fit fractions and interference terms) from the MC Gram
+// matrix and the couplings in theta.
+hipError_t launch_phi(const double* gram, const double* theta, int K, double* phi, hipStream_t st);
 // num <- num / G, dnum <- d(num / G) with G, dG from the full model's
 // partial vector.
 hipError_t launch_ff_finish(const double* dd, int K, int P, double* num, double* dnum,

@@ -1,9 +1,10 @@
 // Small kernels for the quantities read off at a minimum: the full Hessian
-// (from forward-over-reverse passes along unit directions) and the fit
+// (from forward-over-reverse passes along unit directions), the fit
 // fractions with their gradients (from MC-only passes with all but one
-// coupling switched off).  The event passes themselves are the likelihood
-// kernels; these kernels only prepare directions and masked parameter
-// vectors and rearrange the per-pass results.
+// coupling switched off) and the fraction matrix with the interference
+// terms (from the MC Gram matrix).  The event passes themselves are the
+// likelihood and Gram kernels; these kernels only prepare directions and
+// masked parameter vectors and rearrange the per-pass results.
 
 #include "pwa_analysis.h"
 
@@ -70,6 +71,39 @@ __global__ __launch_bounds__(1024) void ff_finish_kernel(const double* __restric
   for (int k = threadIdx.x; k < K; k += blockDim.x) num[k] = num[k] * rG;
 }
 
+// Fraction matrix from the MC Gram matrix Gm[k][l] = sum_MC conj(a_k) a_l
+// ((re, im) pairs, row-major) and the couplings in theta: with
+// y_k = c_k a_k, sum_MC conj(y_k) y_l = conj(c_k) c_l Gm[k][l], so
+//   D = sum_kl Re(conj(c_k) c_l Gm[k][l]) = sum_MC |z|^2,
+//   phi[k][k] = |c_k|^2 Re Gm[k][k] / D,
+//   phi[k][l] = 2 Re(conj(c_k) c_l Gm[k][l]) / D  (k < l),  0 below.
+// One block; D is summed in a fixed order by thread 0.
+__global__ __launch_bounds__(1024) void phi_kernel(const double* __restrict__ gram,
+                                                   const double* __restrict__ theta, int K,
+                                                   double* __restrict__ phi) {
+  __shared__ double sD;
+  auto term = [&](int k, int l) {
+    const double ckr = theta[4 * k], cki = theta[4 * k + 1];
+    const double clr = theta[4 * l], cli = theta[4 * l + 1];
+    // conj(c_k) c_l
+    const double pr = ckr * clr + cki * cli, pi = ckr * cli - cki * clr;
+    const double gr = gram[2 * (k * K + l)], gi = gram[2 * (k * K + l) + 1];
+    return pr * gr - pi * gi;
+  };
+  if (threadIdx.x == 0) {
+    double D = 0.0;
+    for (int k = 0; k < K; ++k)
+      for (int l = 0; l < K; ++l) D += term(k, l);
+    sD = D;
+  }
+  __syncthreads();
+  const double rD = 1.0 / sD;
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
+    const int k = i / K, l = i % K;
+    phi[i] = (l < k) ? 0.0 : (l == k ? term(k, k) : 2.0 * term(k, l)) * rD;
+  }
+}
+
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 hipError_t launch_unit(double* v, int P, int j, hipStream_t st) {
@@ -93,6 +127,11 @@ hipError_t launch_ff_take(const double* dd, int P, int k, double* num, double* d
                           hipStream_t st) {
   hipLaunchKernelGGL(ff_take_kernel, dim3(blocks_for(P, 256)), dim3(256), 0, st, dd, P, k, num,
                      dnum);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi(const double* gram, const double* theta, int K, double* phi, hipStream_t st) {
+  hipLaunchKernelGGL(phi_kernel, dim3(1), dim3(1024), 0, st, gram, theta, K, phi);
   return hipGetLastError();
 }
 

@@ -1128,6 +1128,37 @@ int pwa_fit_fractions(pwa_ctx* c, const double* d_theta, double* d_ff, double* d
   return launch_ff_finish(c->dd, K, P, d_ff, d_dff, st) == hipSuccess ? PWA_OK : PWA_E_HIP;
 }
 
+// Fraction matrix: MC Gram matrix at theta's masses and widths (the batched
+// path's FP64 matrix-core Gram kernel), then the coupling contraction.
+constexpr int kPhiGramBlocks = 512;
+constexpr int kPhiGP = 48;   // padded 2K of the Gram kernel (K <= 24)
+
+size_t pwa_fraction_matrix_workspace_bytes(const pwa_ctx* c) {
+  if (!c || c->K > 24 || !(c->streams & PWA_STREAM_F64)) return 0;
+  return align_up(sizeof(double) * 2 * (size_t)kPhiGramBlocks * kPhiGP * kPhiGP, 256) +
+         align_up(sizeof(double) * 2 * (size_t)c->K * c->K, 256);
+}
+
+int pwa_fraction_matrix(pwa_ctx* c, const double* d_theta, void* d_ws, size_t ws_bytes,
+                        double* d_phi, hipStream_t st) {
+  if (!c || !d_theta || !d_phi) return PWA_E_INVALID;
+  const size_t need = pwa_fraction_matrix_workspace_bytes(c);
+  if (need == 0) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  if (!d_ws || ((uintptr_t)d_ws % 256) != 0 || ws_bytes < need) return PWA_E_WORKSPACE;
+  c->hvp_cache = false;
+  double* part = (double*)d_ws;
+  double* gram = (double*)((char*)d_ws +
+                           align_up(sizeof(double) * 2 * (size_t)kPhiGramBlocks * kPhiGP * kPhiGP, 256));
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kPhiGramBlocks, (c->n_mc + 255) / 256));
+  if (launch_table(d_theta, nullptr, c->md, c->K, c->tbl64, c->tbl32, c->itbl, c->status, st) != hipSuccess)
+    return PWA_E_HIP;
+  if (launch_gram(c->planes64, c->stride, c->n_data, c->n_mc, c->tbl64, c->itbl, c->K, blocks, part,
+                  gram, st) != hipSuccess)
+    return PWA_E_HIP;
+  return launch_phi(gram, d_theta, c->K, d_phi, st) == hipSuccess ? PWA_OK : PWA_E_HIP;
+}
+
 int pwa_covariance(int32_t P, const double* H, const uint8_t* free_mask, double* cov) {
   if (P < 1 || P > 4 * PWA_MAX_RES || !H || !cov) return PWA_E_INVALID;
   std::vector<int> idx;

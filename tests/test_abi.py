@@ -123,6 +123,10 @@ def test_unbound_and_bad_bind_arguments(lib):
         assert lib.pwa_intensity(h, fake, 0, fake, st) == L.PWA_E_STATE
         assert lib.pwa_hessian(h, fake, fake, st) == L.PWA_E_STATE
         assert lib.pwa_hvp_reuse(h, fake, fake, None, None, st) == L.PWA_E_STATE
+        nb = lib.pwa_fraction_matrix_workspace_bytes(h)
+        assert nb > 0
+        assert lib.pwa_fraction_matrix(h, fake, fake, nb, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_fraction_matrix(h, None, fake, nb, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_hvp_reuse(h, None, fake, None, None, st) == L.PWA_E_INVALID
         assert lib.pwa_hessian(h, None, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_fit_fractions(h, fake, fake, None, st) == L.PWA_E_STATE
@@ -267,3 +271,15 @@ def test_propagate():
     np.testing.assert_allclose(propagate(J, C), np.sqrt(np.einsum("ri,ij,rj->r", J, C, J)),
                                rtol=1e-13)
     assert propagate(np.zeros((1, 10)), C)[0] == 0.0
+
+
+def test_fraction_matrix_limits(lib):
+    """The Gram route serves K <= 24 with an FP64 event stream only."""
+    for K, streams, ok in ((24, L.PWA_STREAM_F64, True), (25, L.PWA_STREAM_F64, False),
+                           (6, L.PWA_STREAM_F32, False)):
+        code, h = _create(lib, _model(K), streams)
+        assert code == L.PWA_OK
+        try:
+            assert (lib.pwa_fraction_matrix_workspace_bytes(h) > 0) == ok
+        finally:
+            lib.pwa_destroy(h)

@@ -221,3 +221,21 @@ def test_fp32_stream_hessian_and_fractions():
     Fo, dFo = oracle.fit_fractions(mc, model, th)
     np.testing.assert_allclose(_np(F), Fo, rtol=1e-5)
     np.testing.assert_allclose(_np(dF), dFo, rtol=1e-4, atol=1e-5 * (1.0 + np.max(np.abs(dFo))))
+
+
+@pytest.mark.parametrize("K,nm,seed", [(1, 3001, 81), (2, 9013, 82), (6, 7001, 83), (12, 12007, 84),
+                                       (24, 5003, 85)])
+def test_fraction_matrix_parity(K, nm, seed):
+    """Fit fractions and interference terms from the FP64 matrix-core Gram
+    matrix against the oracle's direct sums; they add up to 1, and the
+    diagonal equals pwa_fit_fractions (masked gradient passes)."""
+    say(f"[fraction matrix] K={K} nm={nm}")
+    model, th, data, mc, _ = case(K, 301, nm, seed)
+    lik = likelihood(model, data, mc)
+    Phi = _np(lik.fraction_matrix(th))
+    Po = oracle.fraction_matrix(mc, model, th)
+    np.testing.assert_allclose(Phi, Po, rtol=1e-10, atol=1e-12)
+    assert abs(Phi.sum() - 1.0) <= 1e-12
+    assert np.all(np.tril(Phi, -1) == 0.0)
+    F = _np(lik.fit_fractions(th, with_grad=False))
+    np.testing.assert_allclose(np.diag(Phi), F, rtol=1e-11)
