@@ -271,14 +271,16 @@ def entry_point_times(lik, th, v, reps=20):
 
 def at_minimum_times(lik, th, reps=3):
     """Wall time of the quantities read off at a minimum on the same events:
-    the full Hessian (pwa_hessian, P Hessian-vector passes) and the fit
+    the full Hessian (pwa_hessian, P Hessian-vector passes), the fit
     fractions with their gradients (pwa_fit_fractions, K + 1 MC-only
-    gradient passes), FP64 event stream."""
+    gradient passes) and the fraction matrix with interference terms
+    (pwa_fraction_matrix, one MC Gram pass), FP64 event stream."""
     import torch
     lik.set_precision("f64")
     out = {}
     for name, fn in (("hessian", lambda: lik.hessian(th)),
-                     ("fit_fractions", lambda: lik.fit_fractions(th))):
+                     ("fit_fractions", lambda: lik.fit_fractions(th)),
+                     ("fraction_matrix", lambda: lik.fraction_matrix(th))):
         fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
