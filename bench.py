@@ -81,10 +81,11 @@ def make_workload():
     import torch
     import synth
     from paper_2403_09225_amd.toys import ToyGenerator
-    W = synth.workload(1)
-    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(1, synth.configs.STREAM_MC))
+    W = synth.workload("k12_hvp")
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for("k12_hvp", synth.workloads.STREAM_MC))
     gen = torch.Generator(device="cuda")
-    gen.manual_seed(240309225 + 100 + synth.configs.STREAM_DATA)
+    wl = synth.workloads
+    gen.manual_seed(wl.BASE_SEED + 100 * wl.SEED_INDEX["k12_hvp"] + wl.STREAM_DATA)
     d12, d13 = ToyGenerator(W.channel, W.spin).draw(W.theta_true, W.n_data, gen)
     data = (d12.cpu().numpy(), d13.cpu().numpy())
     return W, data, mc
@@ -161,7 +162,7 @@ def fit_compare(lik, W, cap_s=60.0, n_starts=5):
     Per variant: the first start in detail, and the totals over n_starts
     starts."""
     import synth
-    rng = synth.rng_for(1, synth.configs.STREAM_TEST)
+    rng = synth.rng_for("k12_hvp", synth.workloads.STREAM_TEST)
     starts = [W.theta_true + rng.normal(scale=np.tile([0.02, 0.02, 0.002, 0.002], W.n_res))
               for _ in range(n_starts)]
     out = {}
@@ -207,10 +208,10 @@ def k30_bench(steps=20):
     import torch
     import synth
     from paper_2403_09225_amd import Likelihood
-    W = synth.workload(3)
-    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(3, synth.configs.STREAM_MC))
+    W = synth.workload("k30_diff")
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for("k30_diff", synth.workloads.STREAM_MC))
     data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
-                               synth.rng_for(3, synth.configs.STREAM_DATA))
+                               synth.rng_for("k30_diff", synth.workloads.STREAM_DATA))
     lik = Likelihood(W.channel, W.spin, streams=("f64", "f32")).bind(data[0], data[1], mc[0], mc[1])
     del data, mc
     th = torch.tensor(W.theta_true, dtype=torch.float64, device="cuda")
@@ -299,12 +300,12 @@ def batched_bench(reps=5):
     import torch
     import synth
     from paper_2403_09225_amd import Likelihood
-    W = synth.workload(2)
-    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(2, synth.configs.STREAM_MC))
+    W = synth.workload("k20_batched")
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for("k20_batched", synth.workloads.STREAM_MC))
     data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
-                               synth.rng_for(2, synth.configs.STREAM_DATA))
+                               synth.rng_for("k20_batched", synth.workloads.STREAM_DATA))
     B = W.extra["n_starts"]
-    r = synth.rng_for(2, synth.configs.STREAM_TEST)
+    r = synth.rng_for("k20_batched", synth.workloads.STREAM_TEST)
     C = r.uniform(0, 1, (W.n_res, B)) * np.exp(2j * np.pi * r.uniform(size=(W.n_res, B)))
     lik = Likelihood(W.channel, W.spin).bind(data[0], data[1], mc[0], mc[1])
     del data, mc
@@ -362,8 +363,8 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the likelihood on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md but not launched). Use --gpus 1.",
+        print("bench.py measures one GPU: the sharded evaluation (pwa_partials on each rank, "
+              "one exchange, pwa_combine) is not launched by it. Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

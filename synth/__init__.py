@@ -8,7 +8,7 @@ the HIP library, each written separately. Where a generator needs an
 intensity (accept-reject), the caller passes it in.
 """
 
-from .configs import (  # noqa: F401
+from .workloads import (  # noqa: F401
     PARENT_MASS, DAUGHTER_MASSES, R_BARRIER, CHANNEL_PAIRS,
     Workload, workload, rng_for, draw_theta, resonance_layout,
 )

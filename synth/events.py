@@ -8,7 +8,7 @@ a caller-supplied function.
 
 import numpy as np
 
-from .configs import PARENT_MASS, DAUGHTER_MASSES, CHANNEL_PAIRS
+from .workloads import PARENT_MASS, DAUGHTER_MASSES, CHANNEL_PAIRS
 
 
 def _sum_sq(parent=PARENT_MASS, masses=DAUGHTER_MASSES):

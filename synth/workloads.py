@@ -31,9 +31,14 @@ BASE_SEED = 240309225
 STREAM_MODEL, STREAM_MC, STREAM_DATA, STREAM_TEST = 0, 1, 2, 3
 
 
-def rng_for(cfg: int, stream: int) -> np.random.Generator:
-    """Seeded generator for workload `cfg` and random stream `stream`."""
-    return np.random.Generator(np.random.PCG64(BASE_SEED + 100 * cfg + stream))
+# Workload names and the seed index of each (seeds are BASE_SEED + 100 *
+# index + stream, so every workload draws from its own streams).
+SEED_INDEX = {"k2_fit": 0, "k12_hvp": 1, "k20_batched": 2, "k30_diff": 3, "k12_toys": 4}
+
+
+def rng_for(name: str, stream: int) -> np.random.Generator:
+    """Seeded generator for workload `name` and random stream `stream`."""
+    return np.random.Generator(np.random.PCG64(BASE_SEED + 100 * SEED_INDEX[name] + stream))
 
 
 def threshold(channel: int) -> float:
@@ -74,7 +79,7 @@ def draw_theta(channel, spin, rng: np.random.Generator,
 @dataclass
 class Workload:
     """One synthetic workload: model layout, true parameters and sizes."""
-    cfg: int
+    key: str
     name: str
     n_res: int
     channel: List[int]
@@ -93,35 +98,38 @@ class Workload:
         return 4 * self.n_res
 
 
-def workload(cfg: int) -> Workload:
-    """The five workloads of the build (0 = CPU-sized fit, 1 = GPU-scale
-    NLL/grad/HVP, 2 = batched fixed-lineshape multi-start, 3 = large
-    differentiation, 4 = learned start)."""
-    if cfg == 0:
+def workload(key: str) -> Workload:
+    """The synthetic workloads by name:
+        k2_fit      K = 2 in channel (12), J = 0, 1; 10k data / 50k MC (CPU-sized fit)
+        k12_hvp     K = 12 over three channels; 1M data / 5M MC (NLL, gradient, HVP)
+        k20_batched K = 20, frozen lineshapes; 2M data / 10M MC, 256 starts
+        k30_diff    K = 30; 4M data / 20M MC (large differentiation)
+        k12_toys    K = 12 toys for the start proposal"""
+    if key == "k2_fit":
         c2 = 0.6 * np.exp(1.2j)
         th = np.array([1.0, 0.0, 0.90, 0.10, c2.real, c2.imag, 0.892, 0.05])
-        return Workload(0, "cpu-sized K=2 channel (12), J=0,1", 2, [0, 0], [0, 1],
+        return Workload(key, "cpu-sized K=2 channel (12), J=0,1", 2, [0, 0], [0, 1],
                         th, n_data=10_000, n_mc=50_000)
-    if cfg in (1, 4):
+    if key in ("k12_hvp", "k12_toys"):
         ch, sp = resonance_layout(12)
-        th = draw_theta(ch, sp, rng_for(cfg, STREAM_MODEL))
-        if cfg == 1:
-            return Workload(1, "gpu-scale K=12, 1M data / 5M MC", 12, ch, sp, th,
+        th = draw_theta(ch, sp, rng_for(key, STREAM_MODEL))
+        if key == "k12_hvp":
+            return Workload(key, "gpu-scale K=12, 1M data / 5M MC", 12, ch, sp, th,
                             n_data=1_000_000, n_mc=5_000_000)
-        return Workload(4, "learned-start K=12 toys", 12, ch, sp, th,
+        return Workload(key, "learned-start K=12 toys", 12, ch, sp, th,
                         n_data=50_000, n_mc=500_000,
                         extra={"n_train_toys": 20_000, "n_eval_toys": 200,
                                "eval_n_data": 1_000_000, "eval_n_mc": 5_000_000,
                                "n_random_starts": 256, "hist_bins": 32})
-    if cfg == 2:
+    if key == "k20_batched":
         ch, sp = resonance_layout(20)
-        th = draw_theta(ch, sp, rng_for(2, STREAM_MODEL))
-        return Workload(2, "batched fixed-lineshape K=20, 2M data / 10M MC, B=256",
+        th = draw_theta(ch, sp, rng_for(key, STREAM_MODEL))
+        return Workload(key, "batched fixed-lineshape K=20, 2M data / 10M MC, B=256",
                         20, ch, sp, th, n_data=2_000_000, n_mc=10_000_000,
                         extra={"n_starts": 256})
-    if cfg == 3:
+    if key == "k30_diff":
         ch, sp = resonance_layout(30)
-        th = draw_theta(ch, sp, rng_for(3, STREAM_MODEL))
-        return Workload(3, "differentiation K=30, 4M data / 20M MC", 30, ch, sp, th,
+        th = draw_theta(ch, sp, rng_for(key, STREAM_MODEL))
+        return Workload(key, "differentiation K=30, 4M data / 20M MC", 30, ch, sp, th,
                         n_data=4_000_000, n_mc=20_000_000)
-    raise ValueError(f"unknown workload {cfg}")
+    raise ValueError(f"unknown workload {key}")

@@ -129,23 +129,23 @@ def test_error_matrix_after_fit():
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    W = synth.workload(1)
+def k12_hvp():
+    W = synth.workload("k12_hvp")
     say("[errors fullsize] generating 1M + 5M events")
-    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(1, synth.configs.STREAM_MC))
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for("k12_hvp", synth.workloads.STREAM_MC))
     data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
-                               synth.rng_for(1, synth.configs.STREAM_DATA))
+                               synth.rng_for("k12_hvp", synth.workloads.STREAM_DATA))
     lik = likelihood(W, data, mc, streams=("f64", "f32"))
     return W, data, mc, lik
 
 
-def test_fullsize_hessian_identities(cfg1):
+def test_fullsize_hessian_identities(k12_hvp):
     """At 1M + 5M events: H (J theta) = J g and H (Pi theta) = -Pi g (the
     coupling phase and scale symmetries), and every column equals pwa_hvp
     along that unit vector to rounding (the symmetrisation averages it with
     row j)."""
-    W, data, mc, lik = cfg1
-    th = W.theta_true + synth.rng_for(1, 4).normal(scale=0.01, size=48)
+    W, data, mc, lik = k12_hvp
+    th = W.theta_true + synth.rng_for("k12_hvp", 4).normal(scale=0.01, size=48)
     H = _np(lik.hessian(th))
     _, g = lik.grad(th)
     g = _np(g)
@@ -167,11 +167,11 @@ def test_fullsize_hessian_identities(cfg1):
         assert np.max(np.abs(H[:, j] - hv)) <= 1e-10 * np.max(np.abs(hv))
 
 
-def test_fullsize_fit_fractions(cfg1):
+def test_fullsize_fit_fractions(k12_hvp):
     """At 5M MC events: F_k against the oracle's direct sums over all of
     them; dF through its symmetry identities and a central difference of the
     GPU fractions."""
-    W, data, mc, lik = cfg1
+    W, data, mc, lik = k12_hvp
     th = W.theta_true
     F, dF = lik.fit_fractions(th)
     F, dF = _np(F), _np(dF)
@@ -185,7 +185,7 @@ def test_fullsize_fit_fractions(cfg1):
     scale = np.abs(dF) @ np.abs(th)
     assert np.all(np.abs(dF @ Jt) <= 1e-10 * scale)
     assert np.all(np.abs(dF @ Pt) <= 1e-10 * scale)
-    d = synth.rng_for(1, 5).normal(size=48)
+    d = synth.rng_for("k12_hvp", 5).normal(size=48)
     h = 1e-6
     Fp = _np(lik.fit_fractions(th + h * d, with_grad=False))
     Fm = _np(lik.fit_fractions(th - h * d, with_grad=False))

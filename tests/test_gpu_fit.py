@@ -21,13 +21,13 @@ def say(*a):
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    W = synth.workload(0)
-    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(0, synth.configs.STREAM_MC))
+def k2_fit():
+    W = synth.workload("k2_fit")
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for("k2_fit", synth.workloads.STREAM_MC))
     data = synth.accept_reject(
         W.n_data, lambda x, y: oracle.intensity((x, y), W, W.theta_true),
-        synth.rng_for(0, synth.configs.STREAM_DATA), scan=200_000, batch=1 << 16)
-    rng = synth.rng_for(0, synth.configs.STREAM_TEST)
+        synth.rng_for("k2_fit", synth.workloads.STREAM_DATA), scan=200_000, batch=1 << 16)
+    rng = synth.rng_for("k2_fit", synth.workloads.STREAM_TEST)
     th0 = W.theta_true + rng.normal(scale=[0.1, 0.1, 0.01, 0.01] * 2)
     ref = oracle.newton_cg_fit(data, mc, W, th0, xtol=1e-8)
     return W, data, mc, th0, ref
@@ -42,9 +42,9 @@ def _gauge(th):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_fit_matches_scipy_newton_cg(cfg0, prec):
-    W, data, mc, th0, ref = cfg0
-    say(f"[fit cfg0] hvp precision {prec}")
+def test_fit_matches_scipy_newton_cg(k2_fit, prec):
+    W, data, mc, th0, ref = k2_fit
+    say(f"[fit k2_fit] hvp precision {prec}")
     lik = likelihood(W, data, mc, streams=("f64", "f32"))
     th, rep = lik.fit(th0, xtol=1e-8, hvp_precision=prec)
     th = th.cpu().numpy()
@@ -56,8 +56,8 @@ def test_fit_matches_scipy_newton_cg(cfg0, prec):
     np.testing.assert_allclose(_gauge(th)[2:], _gauge(ref.x)[2:], rtol=0, atol=2e-5)
 
 
-def test_fit_options(cfg0):
-    W, data, mc, th0, ref = cfg0
+def test_fit_options(k2_fit):
+    W, data, mc, th0, ref = k2_fit
     say("[fit options] time cap, free mask")
     lik = likelihood(W, data, mc)
     # a zero-length time budget stops at once with the start point
@@ -74,10 +74,10 @@ def test_fit_options(cfg0):
 
 
 @pytest.mark.parametrize("forcing", ["scipy", "relative"])
-def test_preconditioned_fit_same_minimum(cfg0, forcing):
+def test_preconditioned_fit_same_minimum(k2_fit, forcing):
     """CG preconditioned with |H|^-1 reaches the scipy fit's minimum, with
     and without a fixed coupling (the fixed case has no null direction)."""
-    W, data, mc, th0, ref = cfg0
+    W, data, mc, th0, ref = k2_fit
     say(f"[fit precondition] forcing {forcing}")
     lik = likelihood(W, data, mc)
     th, rep = lik.fit(th0, xtol=1e-8, forcing=forcing, precondition=True)

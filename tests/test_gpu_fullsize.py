@@ -23,12 +23,12 @@ def say(*a):
 
 
 @pytest.fixture(scope="module")
-def cfg1():
-    W = synth.workload(1)
+def k12_hvp():
+    W = synth.workload("k12_hvp")
     say("[fullsize] generating 1M + 5M events")
-    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(1, synth.configs.STREAM_MC))
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for("k12_hvp", synth.workloads.STREAM_MC))
     data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
-                               synth.rng_for(1, synth.configs.STREAM_DATA))
+                               synth.rng_for("k12_hvp", synth.workloads.STREAM_DATA))
     lik = likelihood(W, data, mc, streams=("f64", "f32"))
     return W, data, mc, lik
 
@@ -37,8 +37,8 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def test_fullsize_nll_against_oracle(cfg1):
-    W, data, mc, lik = cfg1
+def test_fullsize_nll_against_oracle(k12_hvp):
+    W, data, mc, lik = k12_hvp
     say("[fullsize] NLL vs oracle over 6M events")
     th = W.theta_true
     ref = oracle.nll(data, mc, W, th)
@@ -52,11 +52,11 @@ def test_fullsize_nll_against_oracle(cfg1):
         lik.set_precision("f64")
 
 
-def test_fullsize_invariance_identities(cfg1):
+def test_fullsize_invariance_identities(k12_hvp):
     """g . J theta = 0, H (J theta) = J g; g . Pi theta = 0, H (Pi theta) = -Pi g."""
-    W, data, mc, lik = cfg1
+    W, data, mc, lik = k12_hvp
     say("[fullsize] invariance identities")
-    th = W.theta_true + synth.rng_for(1, 3).normal(scale=0.01, size=48)
+    th = W.theta_true + synth.rng_for("k12_hvp", 3).normal(scale=0.01, size=48)
     Jt = np.zeros(48)
     Jt[0::4], Jt[1::4] = -th[1::4], th[0::4]
     Pt = np.zeros(48)
@@ -75,13 +75,13 @@ def test_fullsize_invariance_identities(cfg1):
     assert np.max(np.abs(hvP + Pg)) <= 1e-9 * max(np.max(np.abs(hvP)), gmax)
 
 
-def test_fullsize_central_differences(cfg1):
+def test_fullsize_central_differences(k12_hvp):
     """Directional derivative of the GPU NLL (central difference, h = 1e-6)
     equals g . d, and the difference of GPU gradients equals H d."""
-    W, data, mc, lik = cfg1
+    W, data, mc, lik = k12_hvp
     say("[fullsize] central differences")
     th = W.theta_true
-    d = synth.rng_for(1, 4).normal(size=48)
+    d = synth.rng_for("k12_hvp", 4).normal(size=48)
     h = 1e-6
     hv, _, g = lik.hvp(th, d)
     fp = float(lik.grad(th + h * d)[0])
@@ -99,12 +99,12 @@ def test_fullsize_central_differences(cfg1):
     assert np.max(np.abs(hfd - _np(hv))) <= 1e-5 * np.max(np.abs(_np(hv)))
 
 
-def test_fullsize_shards_and_determinism(cfg1):
-    W, data, mc, lik = cfg1
+def test_fullsize_shards_and_determinism(k12_hvp):
+    W, data, mc, lik = k12_hvp
     say("[fullsize] shard identity, determinism")
     from paper_2403_09225_amd import combine
     th = W.theta_true
-    v = synth.rng_for(1, 5).normal(size=48)
+    v = synth.rng_for("k12_hvp", 5).normal(size=48)
     a = lik.hvp(th, v)
     b = lik.hvp(th, v)
     for x, y in zip(a, b):

@@ -32,12 +32,12 @@ def say(*a):
 
 
 @pytest.fixture(scope="module")
-def cfg3():
-    W = synth.workload(3)
-    say(f"[cfg3] generating {W.n_data} + {W.n_mc} events, K = {W.n_res}")
-    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for(3, synth.configs.STREAM_MC))
+def k30_diff():
+    W = synth.workload("k30_diff")
+    say(f"[k30_diff] generating {W.n_data} + {W.n_mc} events, K = {W.n_res}")
+    mc = synth.uniform_phase_space(W.n_mc, synth.rng_for("k30_diff", synth.workloads.STREAM_MC))
     data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
-                               synth.rng_for(3, synth.configs.STREAM_DATA))
+                               synth.rng_for("k30_diff", synth.workloads.STREAM_DATA))
     lik = likelihood(W, data, mc, streams=("f64", "f32"))
     return W, data, mc, lik
 
@@ -46,13 +46,13 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-def test_cfg3_subsample_against_oracle(cfg3):
-    W, data, mc, _ = cfg3
-    say("[cfg3] 50k + 250k subsample vs oracle")
+def test_k30_subsample_against_oracle(k30_diff):
+    W, data, mc, _ = k30_diff
+    say("[k30_diff] 50k + 250k subsample vs oracle")
     d = (data[0][:50_000], data[1][:50_000])
     m = (mc[0][:250_000], mc[1][:250_000])
     model = Model(W.channel, W.spin)
-    v = synth.rng_for(3, synth.configs.STREAM_TEST).normal(size=W.n_par)
+    v = synth.rng_for("k30_diff", synth.workloads.STREAM_TEST).normal(size=W.n_par)
     f, g, hv, S, SH = oracle_all(model, d, m, W.theta_true, v)
     lik = likelihood(model, d, m)
     hv_g, f_g, g_g = lik.hvp(W.theta_true, v)
@@ -61,11 +61,11 @@ def test_cfg3_subsample_against_oracle(cfg3):
     assert_close("hvp", _np(hv_g), hv, SH, 1e-10)
 
 
-def test_cfg3_central_differences(cfg3):
-    W, data, mc, lik = cfg3
-    say("[cfg3] central differences over 24M events")
+def test_k30_central_differences(k30_diff):
+    W, data, mc, lik = k30_diff
+    say("[k30_diff] central differences over 24M events")
     th = W.theta_true
-    d = synth.rng_for(3, 6).normal(size=W.n_par)
+    d = synth.rng_for("k30_diff", 6).normal(size=W.n_par)
     hv, _, g = lik.hvp(th, d)
     g, hv = _np(g), _np(hv)
 
@@ -82,11 +82,11 @@ def test_cfg3_central_differences(cfg3):
     assert np.max(np.abs(hfd - hv)) <= 1e-5 * np.max(np.abs(hv))
 
 
-def test_cfg3_fp32_stream_tracks_fp64(cfg3):
-    W, data, mc, lik = cfg3
-    say("[cfg3] FP32 stream vs FP64 stream")
+def test_k30_fp32_stream_tracks_fp64(k30_diff):
+    W, data, mc, lik = k30_diff
+    say("[k30_diff] FP32 stream vs FP64 stream")
     th = W.theta_true
-    v = synth.rng_for(3, 7).normal(size=W.n_par)
+    v = synth.rng_for("k30_diff", 7).normal(size=W.n_par)
     hv64, f64, g64 = [_np(x) for x in lik.hvp(th, v)]
     lik.set_precision("f32")
     try:
@@ -98,12 +98,12 @@ def test_cfg3_fp32_stream_tracks_fp64(cfg3):
     assert np.max(np.abs(hv32 - hv64)) <= 1e-3 * np.max(np.abs(hv64))
 
 
-def test_cfg3_autograd_double_backward(cfg3):
-    W, data, mc, lik = cfg3
-    say("[cfg3] autograd double backward")
+def test_k30_autograd_double_backward(k30_diff):
+    W, data, mc, lik = k30_diff
+    say("[k30_diff] autograd double backward")
     from paper_2403_09225_amd import nll as nll_fn
     th = torch.tensor(W.theta_true, dtype=torch.float64, device="cuda", requires_grad=True)
-    v = torch.tensor(synth.rng_for(3, 8).normal(size=W.n_par), dtype=torch.float64, device="cuda")
+    v = torch.tensor(synth.rng_for("k30_diff", 8).normal(size=W.n_par), dtype=torch.float64, device="cuda")
     f = nll_fn(th, lik)
     (g,) = torch.autograd.grad(f, th, create_graph=True)
     (hv,) = torch.autograd.grad(g, th, grad_outputs=v)
@@ -116,8 +116,8 @@ def test_cfg3_autograd_double_backward(cfg3):
     assert torch.equal(hv, hv_ref)
 
 
-def test_cfg3_memory_is_the_event_stream(cfg3):
-    W, _, _, lik = cfg3
+def test_k30_memory_is_the_event_stream(k30_diff):
+    W, _, _, lik = k30_diff
     n = W.n_data + W.n_mc
     grow = lik.workspace_bytes(W.n_data, W.n_mc) - lik.workspace_bytes(0, 1)
     stream = 18 * (8 + 4) * n          # FP64 and FP32 planes

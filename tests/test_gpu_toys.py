@@ -50,12 +50,12 @@ def test_intensity_matches_oracle(K):
 
 def test_toys_follow_the_intensity():
     from paper_2403_09225_amd.toys import ToyGenerator
-    W = synth.workload(0)
+    W = synth.workload("k2_fit")
     model = Model(W.channel, W.spin)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(2403)
     n = 200_000
-    say("[toys] drawing 200k events (cfg0 model)")
+    say("[toys] drawing 200k events (k2_fit model)")
     tg = ToyGenerator(W.channel, W.spin, batch=1 << 20, scan=1 << 18)
     s12, s13 = tg.draw(W.theta_true, n, gen)
     s12, s13 = s12.cpu().numpy(), s13.cpu().numpy()

@@ -21,12 +21,12 @@ import synth
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    W = synth.workload(0)
+def k2_fit():
+    W = synth.workload("k2_fit")
     mc = synth.midpoint_grid(500, 500)
     data = synth.accept_reject(
         W.n_data, lambda x, y: oracle.intensity((x, y), W, W.theta_true),
-        synth.rng_for(0, synth.configs.STREAM_DATA), scan=200_000, batch=1 << 16)
+        synth.rng_for("k2_fit", synth.workloads.STREAM_DATA), scan=200_000, batch=1 << 16)
     return W, data, mc
 
 
@@ -40,9 +40,9 @@ def _gauge_fix(th):
 
 
 @pytest.mark.slow
-def test_newton_cg_recovers_truth(cfg0):
-    W, data, mc = cfg0
-    rng = synth.rng_for(0, synth.configs.STREAM_TEST)
+def test_newton_cg_recovers_truth(k2_fit):
+    W, data, mc = k2_fit
+    rng = synth.rng_for("k2_fit", synth.workloads.STREAM_TEST)
     th0 = W.theta_true + rng.normal(scale=[0.1, 0.1, 0.01, 0.01] * 2)
     res = oracle.newton_cg_fit(data, mc, W, th0, xtol=1e-8)
     thf = _gauge_fix(res.x)
