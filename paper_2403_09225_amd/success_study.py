@@ -31,7 +31,7 @@ from .toys import ToyGenerator, uniform_dalitz
 
 def run(K=6, n_events=10_000, n_mc=1_000_000, n_starts=300, xtols=(1e-5, 1e-8), time_cap_s=10.0,
         maxiter=1000, forcing="scipy", tol=1.0, seed=0, log_every=0, device="cuda",
-        precondition=False):
+        precondition=False, early_caps=(0.05, 0.1, 0.2, 0.5, 1.0)):
     """Run the study; returns (summary dict, per-fit rows dict of arrays)."""
     ch, sp = resonance_layout(K)
     prior = Prior.wide(ch)
@@ -94,6 +94,17 @@ def run(K=6, n_events=10_000, n_mc=1_000_000, n_starts=300, xtols=(1e-5, 1e-8), 
             # 1/p, each taking the mean time
             "expected_seconds_to_global": (round(mean_s / rate, 3) if rate > 0 else None),
         }
+        # early stopping at a cap c, from the recorded times: the successes
+        # that finished within c (a lower bound) and the capped mean time
+        caps = {}
+        for c in early_caps:
+            ok_c = ok & (r["seconds"] <= c)
+            t_c = float(np.minimum(r["seconds"], c).mean())
+            caps[f"{c:g}s"] = {"success_rate": float(ok_c.mean()),
+                               "mean_seconds": round(t_c, 4),
+                               "expected_seconds_to_global":
+                                   (round(t_c / ok_c.mean(), 3) if ok_c.any() else None)}
+        summary[key]["early_stop"] = caps
     return summary, rows
 
 
