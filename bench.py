@@ -187,18 +187,19 @@ def fit_compare(lik, W, cap_s=60.0, n_starts=5):
         rec[f"speedup_mixed_vs_fp64_{n_starts}_starts"] = round(rec["f64"][key] / max(rec["f32"][key], 1e-9), 3)
         rec["nll_diff_mixed_minus_fp64"] = rec["f32"]["nll"] - rec["f64"]["nll"]
         out[f"forcing_{forcing}"] = rec
-    # CG preconditioned with |H|^-1 (FP64 HVPs, relative forcing)
-    runs = [lik.fit(start, xtol=1e-8, maxiter=200, time_cap_s=cap_s, forcing="relative",
-                    precondition=True)[1] for start in starts]
-    r0 = runs[0]
-    out["forcing_relative_preconditioned_f64"] = {
-        "seconds": round(r0["seconds"], 4), "nll": r0["nll"], "iterations": r0["iterations"],
-        "hvps": r0["n_hvp"], "grads": r0["n_grad"], "converged": r0["converged"],
-        f"seconds_total_{n_starts}_starts": round(sum(r["seconds"] for r in runs), 4),
-        f"iterations_total_{n_starts}_starts": int(sum(r["iterations"] for r in runs)),
-        f"converged_{n_starts}_starts": int(sum(r["converged"] for r in runs)),
-        "nll_spread": float(max(r["nll"] for r in runs) - min(r["nll"] for r in runs)),
-        "nll_diff_vs_plain_f64": r0["nll"] - out["forcing_relative"]["f64"]["nll"]}
+    # CG preconditioned with |H|^-1 (relative forcing), FP64 and FP32 HVPs
+    for prec in ("f64", "f32"):
+        runs = [lik.fit(start, xtol=1e-8, maxiter=200, time_cap_s=cap_s, forcing="relative",
+                        precondition=True, hvp_precision=prec)[1] for start in starts]
+        r0 = runs[0]
+        out[f"forcing_relative_preconditioned_{prec}"] = {
+            "seconds": round(r0["seconds"], 4), "nll": r0["nll"], "iterations": r0["iterations"],
+            "hvps": r0["n_hvp"], "grads": r0["n_grad"], "converged": r0["converged"],
+            f"seconds_total_{n_starts}_starts": round(sum(r["seconds"] for r in runs), 4),
+            f"iterations_total_{n_starts}_starts": int(sum(r["iterations"] for r in runs)),
+            f"converged_{n_starts}_starts": int(sum(r["converged"] for r in runs)),
+            "nll_spread": float(max(r["nll"] for r in runs) - min(r["nll"] for r in runs)),
+            "nll_diff_vs_plain_f64": r0["nll"] - out["forcing_relative"]["f64"]["nll"]}
     return out
 
 
