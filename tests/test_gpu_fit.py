@@ -73,20 +73,22 @@ def test_fit_options(k2_fit):
     assert rep["nll"] <= ref.fun + 1e-6
 
 
-@pytest.mark.parametrize("forcing", ["scipy", "relative"])
-def test_preconditioned_fit_same_minimum(k2_fit, forcing):
+@pytest.mark.parametrize("forcing,prec", [("scipy", "f64"), ("relative", "f64"), ("relative", "f32")])
+def test_preconditioned_fit_same_minimum(k2_fit, forcing, prec):
     """CG preconditioned with |H|^-1 reaches the scipy fit's minimum, with
-    and without a fixed coupling (the fixed case has no null direction)."""
+    and without a fixed coupling (the fixed case has no null direction),
+    with FP64 or FP32 HVPs inside CG."""
     W, data, mc, th0, ref = k2_fit
-    say(f"[fit precondition] forcing {forcing}")
-    lik = likelihood(W, data, mc)
-    th, rep = lik.fit(th0, xtol=1e-8, forcing=forcing, precondition=True)
+    say(f"[fit precondition] forcing {forcing}, hvp precision {prec}")
+    lik = likelihood(W, data, mc, streams=("f64", "f32"))
+    th, rep = lik.fit(th0, xtol=1e-8, forcing=forcing, precondition=True, hvp_precision=prec)
     say(f"  preconditioned: nll {rep['nll']:.10f} iters {rep['iterations']} hvps {rep['n_hvp']}")
     assert rep["converged"] == 1, rep
     assert abs(rep["nll"] - ref.fun) <= 1e-6
     np.testing.assert_allclose(_gauge(th.cpu().numpy())[2:], _gauge(ref.x)[2:], rtol=0, atol=2e-5)
     mask = [0, 0, 1, 1, 1, 1, 1, 1]
-    th, rep = lik.fit(th0, xtol=1e-8, forcing=forcing, precondition=True, free_mask=mask)
+    th, rep = lik.fit(th0, xtol=1e-8, forcing=forcing, precondition=True, free_mask=mask,
+                      hvp_precision=prec)
     assert rep["converged"] == 1, rep
     np.testing.assert_array_equal(th.cpu().numpy()[:2], th0[:2])
     assert rep["nll"] <= ref.fun + 1e-6
