@@ -154,11 +154,12 @@ int pwa_hvp(pwa_ctx* ctx, const double* d_theta, const double* d_v, double* d_hv
  * eq. (7) product is contracted from, only the three weighted by the
  * direction (the derivative of z along v) depend on v; this pass
  * accumulates those alone and reuses the theta-only totals of that call, so
- * it does about half the per-event work.  Results equal pwa_hvp at that
- * theta up to rounding.  d_nll, d_grad (may be null) receive the NLL and
- * gradient at that theta.  Any other evaluation on the context (pwa_nll,
- * pwa_grad, pwa_partials, pwa_fit, pwa_hessian, pwa_fit_fractions, pwa_bind)
- * ends the reuse: PWA_E_STATE until the next pwa_hvp.  Uses the current
+ * it issues about 60 % of the per-event instructions of a full pass.
+ * Results equal pwa_hvp at that theta up to rounding.  d_nll, d_grad (may
+ * be null) receive the NLL and gradient at that theta.  Any other
+ * evaluation on the context (pwa_nll, pwa_grad, pwa_partials, pwa_fit,
+ * pwa_hessian, pwa_fit_fractions, pwa_fraction_matrix, pwa_bind) ends the
+ * reuse: PWA_E_STATE until the next pwa_hvp.  Uses the current
  * precision (a full pass if the cached totals are of the other one).
  * Errors: PWA_E_INVALID, PWA_E_STATE, PWA_E_HIP. */
 int pwa_hvp_reuse(pwa_ctx* ctx, const double* d_v, double* d_hv, double* d_nll, double* d_grad,
