@@ -148,8 +148,9 @@ int pwa_grad(pwa_ctx* ctx, const double* d_theta, double* d_nll, double* d_grad,
 int pwa_hvp(pwa_ctx* ctx, const double* d_theta, const double* d_v, double* d_hv,
             double* d_nll, double* d_grad, hipStream_t stream);
 
-/* Hessian-vector product at the theta of the last pwa_hvp call on this
- * context, for a new direction d_v (P doubles): Newton-CG evaluates many
+/* Hessian-vector product at the theta of the last pwa_hvp call (or
+ * pwa_partials call with a direction) on this context, for a new direction
+ * d_v (P doubles): Newton-CG evaluates many
  * products at one theta.  Of the per-resonance event moments that the
  * eq. (7) product is contracted from, only the three weighted by the
  * direction (the derivative of z along v) depend on v; this pass
@@ -159,7 +160,8 @@ int pwa_hvp(pwa_ctx* ctx, const double* d_theta, const double* d_v, double* d_hv
  * be null) receive the NLL and gradient at that theta.  Any other
  * evaluation on the context (pwa_nll, pwa_grad, pwa_partials, pwa_fit,
  * pwa_hessian, pwa_fit_fractions, pwa_fraction_matrix, pwa_bind) ends the
- * reuse: PWA_E_STATE until the next pwa_hvp.  Uses the current
+ * reuse: PWA_E_STATE until the next pwa_hvp (or pwa_partials with a
+ * direction).  Uses the current
  * precision (a full pass if the cached totals are of the other one).
  * Errors: PWA_E_INVALID, PWA_E_STATE, PWA_E_HIP. */
 int pwa_hvp_reuse(pwa_ctx* ctx, const double* d_v, double* d_hv, double* d_nll, double* d_grad,
@@ -184,6 +186,13 @@ int pwa_intensity(pwa_ctx* ctx, const double* d_theta, int32_t which, double* d_
  * written as zero. */
 int pwa_partials(pwa_ctx* ctx, const double* d_theta, const double* d_v, double* d_part,
                  hipStream_t stream);
+
+/* pwa_partials with a new direction d_v at the theta of the last pwa_hvp or
+ * pwa_partials-with-direction call on this context, by the direction-only
+ * pass of pwa_hvp_reuse (same rules; PWA_E_STATE without such totals).  On
+ * each rank of a sharded fit this gives the per-shard vector of the CG
+ * products after the first at a Newton iterate. */
+int pwa_partials_reuse(pwa_ctx* ctx, const double* d_v, double* d_part, hipStream_t stream);
 
 /* Combine n_shards partial vectors (layout of pwa_partials, consecutive in
  * d_parts) with eq. (4), (6), (7): NLL, gradient and (if d_hv is non-null)

@@ -65,6 +65,7 @@ SIGNATURES = {
     "pwa_hvp": (c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "pwa_partials": (c_int32, [_P, _P, _P, _P, _P]),
     "pwa_hvp_reuse": (c_int32, [_P, _P, _P, _P, _P, _P]),
+    "pwa_partials_reuse": (c_int32, [_P, _P, _P, _P]),
     "pwa_intensity": (c_int32, [_P, _P, c_int32, _P, _P]),
     "pwa_combine": (c_int32, [c_int32, c_int32, _P, c_int64, c_int64, _P, _P, _P, _P, _P]),
     "pwa_fit": (c_int32, [_P, _P, ctypes.POINTER(PwaFitOpts), ctypes.POINTER(PwaFitReport), _P]),

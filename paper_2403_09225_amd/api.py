@@ -175,6 +175,14 @@ class Likelihood:
         L.check("pwa_partials", self.lib.pwa_partials(self._h, _ptr(t), _ptr(vv), _ptr(out), _stream()))
         return out
 
+    def partials_reuse(self, v):
+        """partials() with a new direction at the theta of the last
+        hvp()/partials(theta, v) call (direction-only pass)."""
+        vv = self._theta(v)
+        out = torch.empty(2 * (2 + 4 * self.n_par), dtype=torch.float64, device=self.device)
+        L.check("pwa_partials_reuse", self.lib.pwa_partials_reuse(self._h, _ptr(vv), _ptr(out), _stream()))
+        return out
+
     def combine(self, parts, n_data_total, n_mc_total, v=None):
         return combine(parts, self.n_par, n_data_total, n_mc_total, v, self.device)
 

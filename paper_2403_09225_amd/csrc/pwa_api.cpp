@@ -206,8 +206,7 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
              const double* d_v, double* d_nll, double* d_grad, double* d_hv, double* d_dd,
              hipStream_t st, bool mc_only = false) {
   int L = 2, T = 1, R = 1;
-  if (mode == MODE_HVPB &&
-      !(c->hvp_cache && c->cache_prec == prec && out_kind == OUT_COMBINED && !mc_only))
+  if (mode == MODE_HVPB && !(c->hvp_cache && c->cache_prec == prec && !mc_only))
     mode = MODE_HVP;
   const bool reuse = (mode == MODE_HVPB);
   c->hvp_cache = false;   // every pass rewrites the totals; set again below
@@ -262,7 +261,7 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
   f.status = c->status;
   e = launch_final(f, st);
   if (e != hipSuccess) return PWA_E_HIP;
-  if (mode == MODE_HVP && out_kind == OUT_COMBINED && !mc_only) {
+  if (mode == MODE_HVP && !mc_only) {
     double* ct = cache_theta_slot(c);
     if (d_theta != ct &&
         hipMemcpyAsync(ct, d_theta, sizeof(double) * c->P, hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -500,6 +499,14 @@ int pwa_hvp_reuse(pwa_ctx* c, const double* d_v, double* d_hv, double* d_nll, do
   if (!c->hvp_cache) return PWA_E_STATE;
   return run_eval(c, MODE_HVPB, OUT_COMBINED, c->precision, cache_theta_slot(c), d_v, d_nll,
                   d_grad, d_hv, nullptr, st);
+}
+
+int pwa_partials_reuse(pwa_ctx* c, const double* d_v, double* d_part, hipStream_t st) {
+  if (!c || !d_v || !d_part) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  if (!c->hvp_cache) return PWA_E_STATE;
+  return run_eval(c, MODE_HVPB, OUT_PARTIALS, c->precision, cache_theta_slot(c), d_v, nullptr,
+                  nullptr, nullptr, d_part, st);
 }
 
 int pwa_intensity(pwa_ctx* c, const double* d_theta, int32_t which, double* d_out,

@@ -128,6 +128,8 @@ def test_unbound_and_bad_bind_arguments(lib):
         assert lib.pwa_fraction_matrix(h, fake, fake, nb, fake, st) == L.PWA_E_STATE
         assert lib.pwa_fraction_matrix(h, None, fake, nb, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_hvp_reuse(h, None, fake, None, None, st) == L.PWA_E_INVALID
+        assert lib.pwa_partials_reuse(h, fake, fake, st) == L.PWA_E_STATE
+        assert lib.pwa_partials_reuse(h, fake, None, st) == L.PWA_E_INVALID
         assert lib.pwa_hessian(h, None, fake, st) == L.PWA_E_INVALID
         assert lib.pwa_fit_fractions(h, fake, fake, None, st) == L.PWA_E_STATE
         assert lib.pwa_fit_fractions(h, fake, None, fake, st) == L.PWA_E_INVALID

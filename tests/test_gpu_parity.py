@@ -135,6 +135,34 @@ def test_partials_and_virtual_shards():
     assert_close("hv shards vs oracle", _np(hv1), hv, SH + S + np.abs(hv), 1e-10)
 
 
+def test_partials_reuse_virtual_shards():
+    """The sharded CG step: three contexts each take pwa_partials at theta
+    with one direction, then pwa_partials_reuse with a new one; the combine
+    of the reused partials equals the unsharded H w and the oracle's."""
+    say("[virtual shards, reuse] K=12")
+    model, th, data, mc, v = case(12, 3001, 12007, 51)
+    from paper_2403_09225_amd import combine
+    w = rng(52).normal(size=48)
+    cd, cm = [0, 1000, 1001, 3001], [0, 5000, 9000, 12007]
+    liks = []
+    for i in range(3):
+        d = (data[0][cd[i]:cd[i + 1]], data[1][cd[i]:cd[i + 1]])
+        m = (mc[0][cm[i]:cm[i + 1]], mc[1][cm[i]:cm[i + 1]])
+        lik = likelihood(model, d, m)
+        lik.partials(th, v)
+        liks.append(lik)
+    parts = [lik.partials_reuse(w) for lik in liks]
+    f1, g1, hv1 = combine(parts, 48, len(data[0]), len(mc[0]), w)
+    f, g, hv, S, SH = oracle_all(model, data, mc, th, w)
+    assert abs(float(f1) - f) <= 1e-10 * abs(f)
+    assert_close("grad reuse shards", _np(g1), g, S, 1e-10)
+    assert_close("hv reuse shards", _np(hv1), hv, SH + S + np.abs(hv), 1e-10)
+    # equal to a full pass per shard to rounding
+    full = [lik.partials(th, w) for lik in liks]
+    _, _, hv2 = combine(full, 48, len(data[0]), len(mc[0]), w)
+    assert np.all(np.abs(_np(hv1) - _np(hv2)) <= 1e-12 * (SH + S + np.abs(hv)))
+
+
 def test_edge_cases():
     say("[edge] empty data, single events, below threshold, zero couplings")
     # no data events: NLL = 0 and gradient 0 (N_D = 0)
