@@ -204,15 +204,19 @@ def fit_compare(lik, W, cap_s=60.0, n_starts=5):
 
 
 def k30_bench(steps=20):
-    """The differentiation workload (K = 30, 4M data + 20M MC): fused
-    NLL+grad+HVP events/s on the FP64 and FP32 streams."""
+    """The differentiation workload (K = 30, 4M data drawn from the model on
+    the GPU + 20M MC): fused NLL+grad+HVP events/s on the FP64 and FP32
+    streams, and the direction-only HVP of the CG inner step."""
     import torch
     import synth
     from paper_2403_09225_amd import Likelihood
+    from paper_2403_09225_amd.toys import ToyGenerator
     W = synth.workload("k30_diff")
     mc = synth.uniform_phase_space(W.n_mc, synth.rng_for("k30_diff", synth.workloads.STREAM_MC))
-    data = synth.resonant_like(W.n_data, W.channel, W.theta_true,
-                               synth.rng_for("k30_diff", synth.workloads.STREAM_DATA))
+    wl = synth.workloads
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(wl.BASE_SEED + 100 * wl.SEED_INDEX["k30_diff"] + wl.STREAM_DATA)
+    data = ToyGenerator(W.channel, W.spin).draw(W.theta_true, W.n_data, gen)
     lik = Likelihood(W.channel, W.spin, streams=("f64", "f32")).bind(data[0], data[1], mc[0], mc[1])
     del data, mc
     th = torch.tensor(W.theta_true, dtype=torch.float64, device="cuda")
@@ -238,6 +242,13 @@ def k30_bench(steps=20):
                      "kernel_us": round(k_ms / max(k_n, 1) * 1e3, 2),
                      "hbm_frac_kernel": round(n * 18 * (8 if prec == "f64" else 4)
                                               / (k_ms / max(k_n, 1) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        lik.hvp(th, v)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lik.hvp_reuse(v)
+        torch.cuda.synchronize()
+        out[prec]["reuse_ms_per_step"] = round((time.perf_counter() - t0) / steps * 1e3, 4)
     return out
 
 
