@@ -998,30 +998,64 @@ __device__ void combine_block(double F, double G, const double* dF, const double
   }
 }
 
-// Stage 1: fixed-order double-double sum of the block partials, coalesced:
-// lane l of a block owns value index blockIdx.x * 64 + l (data values first,
-// then MC values); the 16 waves stride over the partial blocks and are then
-// combined in wave order.
+// Stage 1: fixed-order double-double sum of the block partials.  A block
+// owns 16 value indices (blockIdx.x * 16 + (tid & 15); data values first,
+// then MC values) and its 64 thread groups stride over the partial blocks,
+// each with U independent accumulators; the groups are then combined by a
+// fixed binary tree in LDS.  The order depends only on the grid, so the
+// result is bitwise reproducible.
+constexpr int RED_VALS = 16, RED_GROUPS = 64;
 __global__ __launch_bounds__(1024) void reduce_kernel(FinalArgs f) {
-  __shared__ double red[16][64][2];
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int vv = blockIdx.x * 64 + lane;
+  __shared__ double red[RED_GROUPS][RED_VALS][2];
+  const int col = threadIdx.x % RED_VALS, grp = threadIdx.x / RED_VALS;
+  const int vv = blockIdx.x * RED_VALS + col;
   double hi = 0.0, lo = 0.0;
   if (vv < 2 * f.V) {
     const int set = vv >= f.V;
     const int vi = vv - set * f.V;
     const int b0 = set ? f.nb_data : 0;
     const int nb = set ? f.nb_mc : f.nb_data;
-    for (int b = grp; b < nb; b += 16) {
-      const double* q = f.part + ((int64_t)(b0 + b) * f.V + vi) * 2;
-      dd_add(hi, lo, q[0], q[1]);
+    constexpr int U = 4;
+    double h[U], l[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) h[u] = l[u] = 0.0;
+    int b = grp;
+    for (; b + RED_GROUPS * (U - 1) < nb; b += RED_GROUPS * U) {
+      double qh[U], ql[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double* q = f.part + ((int64_t)(b0 + b + RED_GROUPS * u) * f.V + vi) * 2;
+        qh[u] = q[0];
+        ql[u] = q[1];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) dd_add(h[u], l[u], qh[u], ql[u]);
     }
+    for (; b < nb; b += RED_GROUPS) {
+      const double* q = f.part + ((int64_t)(b0 + b) * f.V + vi) * 2;
+      dd_add(h[0], l[0], q[0], q[1]);
+    }
+    hi = h[0];
+    lo = l[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u) dd_add(hi, lo, h[u], l[u]);
   }
-  red[grp][lane][0] = hi;
-  red[grp][lane][1] = lo;
+  red[grp][col][0] = hi;
+  red[grp][col][1] = lo;
   __syncthreads();
+#pragma unroll
+  for (int half = RED_GROUPS / 2; half > 0; half >>= 1) {
+    if (grp < half) {
+      double a = red[grp][col][0], c = red[grp][col][1];
+      dd_add(a, c, red[grp + half][col][0], red[grp + half][col][1]);
+      red[grp][col][0] = a;
+      red[grp][col][1] = c;
+    }
+    __syncthreads();
+  }
   if (grp == 0 && vv < 2 * f.V) {
-    for (int g = 1; g < 16; ++g) dd_add(hi, lo, red[g][lane][0], red[g][lane][1]);
+    hi = red[0][col][0];
+    lo = red[0][col][1];
     int dst = vv;
     if (f.mode == MODE_HVPB) {
       // direction moments into their slots of the full HVP totals; the
@@ -1284,7 +1318,7 @@ int eval_occupancy(int is_f32, int mode, int layout, int T, int R) {
 }
 
 hipError_t launch_final(const FinalArgs& f, hipStream_t st) {
-  const unsigned nb = (unsigned)((2 * f.V + 63) / 64);
+  const unsigned nb = (unsigned)((2 * f.V + RED_VALS - 1) / RED_VALS);
   hipLaunchKernelGGL(reduce_kernel, dim3(nb), dim3(1024), 0, st, f);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
