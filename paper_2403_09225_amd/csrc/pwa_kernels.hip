@@ -968,7 +968,12 @@ __device__ void combine_block(double F, double G, const double* dF, const double
                               double nm, const double* v, double* nll, double* grad, double* hv,
                               int* status) {
   __shared__ double sc[2];
+  __shared__ double sv[4 * PWA_MAX_RES];
   const int tid = threadIdx.x;
+  // the direction, staged in LDS by all threads (the sum below is serial)
+  if (mode == MODE_HVP && v)
+    for (int p = tid; p < P; p += blockDim.x) sv[p] = v[p];
+  __syncthreads();
   if (tid == 0) {
     double val = -F + nd * log(G / nm);
     int flags = status ? status[0] : 0;
@@ -977,8 +982,8 @@ __device__ void combine_block(double F, double G, const double* dF, const double
     double dh = 0.0, dl = 0.0;
     if (mode == MODE_HVP && v) {
       for (int p = 0; p < P; ++p) {
-        const double prod = dG[p] * v[p];
-        dd_add(dh, dl, prod, fma(dG[p], v[p], -prod));
+        const double prod = dG[p] * sv[p];
+        dd_add(dh, dl, prod, fma(dG[p], sv[p], -prod));
       }
     }
     sc[0] = dh + dl;
