@@ -239,3 +239,31 @@ def test_fraction_matrix_parity(K, nm, seed):
     assert np.all(np.tril(Phi, -1) == 0.0)
     F = _np(lik.fit_fractions(th, with_grad=False))
     np.testing.assert_allclose(np.diag(Phi), F, rtol=1e-11)
+
+
+def test_edge_cases_at_the_minimum():
+    """No data events (MC only), a resonance whose coupling is zero (its
+    fraction, its interference terms and the gradient of its fraction along
+    the other parameters vanish), and an FP32-only context."""
+    model, th, data, mc, _ = case(5, 0, 4001, 90)
+    th = th.copy()
+    th[8:10] = 0.0                                  # c_2 = 0
+    lik = likelihood(model, (np.zeros(0), np.zeros(0)), mc)
+    F, dF = lik.fit_fractions(th)
+    F, dF = _np(F), _np(dF)
+    Fo, dFo = oracle.fit_fractions(mc, model, th)
+    np.testing.assert_allclose(F, Fo, rtol=1e-11, atol=1e-15)
+    assert F[2] == 0.0 and np.all(dF[2] == 0.0)
+    Phi = _np(lik.fraction_matrix(th))
+    np.testing.assert_allclose(Phi, oracle.fraction_matrix(mc, model, th), rtol=1e-10, atol=1e-12)
+    assert np.all(Phi[2, :] == 0.0) and np.all(Phi[:, 2] == 0.0)
+    H = _np(lik.hessian(th))
+    assert np.all(np.isfinite(H)) and np.array_equal(H, H.T)
+    assert lik.device_status() == 0
+    lik32 = likelihood(model, data, mc, streams=("f32",))
+    H32 = _np(lik32.hessian(th))
+    F32 = _np(lik32.fit_fractions(th, with_grad=False))
+    np.testing.assert_allclose(F32, Fo, rtol=1e-5, atol=1e-12)
+    assert np.all(np.isfinite(H32))
+    with pytest.raises(ValueError):
+        lik32.fraction_matrix(th)                   # Gram route needs the FP64 stream
