@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+WARM_SECONDS = 1.5        # minimum untimed warm-up (clock ramp), see main()
 
 
 def hvp_flops_per_event(K, data_fraction):
@@ -404,6 +405,14 @@ def main():
     for _ in range(args.warmup):
         lik.hvp(th, v)
     torch.cuda.synchronize()
+    # Clock ramp: the first few hundred milliseconds of sustained load run at
+    # lower clocks, so untimed steps continue until the warm-up has lasted
+    # WARM_SECONDS of wall time whatever --warmup says.
+    t_w = time.perf_counter()
+    while time.perf_counter() - t_w < WARM_SECONDS:
+        for _ in range(50):
+            lik.hvp(th, v)
+        torch.cuda.synchronize()
     lik.set_kernel_timing(True)
     lik.kernel_time()
     torch.cuda.synchronize()

@@ -302,7 +302,9 @@ int pwa_fraction_matrix(pwa_ctx* ctx, const double* d_theta, void* d_ws, size_t 
  * change when every coupling is multiplied by one complex number, so with
  * all parameters free H is singular: fix one coupling (its real and
  * imaginary parts).  Errors: PWA_E_INVALID (sizes, null, non-finite H),
- * PWA_E_DOMAIN (the free block is not positive definite). */
+ * PWA_E_DOMAIN (the free block is not positive definite, or numerically
+ * singular: a Cholesky pivot at or below 1e-12 n H_jj, n the number of free
+ * parameters, is a direction the Hessian does not resolve above rounding). */
 int pwa_covariance(int32_t P, const double* h_H, const uint8_t* h_free, double* h_cov);
 
 /* Linear error propagation (host arrays): sigma_r = sqrt(J_r C J_r^T) for the

@@ -81,6 +81,24 @@ int pwa_mlp_forward(const pwa_mlp_dims* dims, const float* d_master, const uint1
                     const float* d_x, int32_t batch, float* d_y, void* d_ws, size_t ws_bytes,
                     hipStream_t stream);
 
+/* pwa_mlp_forward without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * propose start points, harnesses that forbid hipMalloc).  Same kernels and
+ * the same results as pwa_mlp_forward; what that call keeps in d_ws lives
+ * instead in a fixed 4 MiB device array inside the library (one copy per GPU,
+ * held until the process ends; the call allocates nothing).  The forward
+ * buffers must fit in it: with the batch rounded up to 16 rows, 4 n_in +
+ * 8 n_h1 + 8 n_h2 bytes per row (each of the 8 buffers rounded up to 256
+ * bytes), e.g. batch <= 336 for 1024 -> 512 -> 512 -> 48; larger batches
+ * return PWA_E_WORKSPACE.  Every call on one GPU shares that GPU's array, so
+ * calls that overlap on one GPU (concurrent streams or threads) race; the
+ * array keeps the last call's contents, and nothing in it needs to start at
+ * zero.  No backward pass can follow this call (use pwa_mlp_forward for
+ * training).  Errors: PWA_E_INVALID, PWA_E_WORKSPACE, PWA_E_HIP. */
+int pwa_mlp_forward_noalloc(const pwa_mlp_dims* dims, const float* d_master,
+                            const uint16_t* d_wbf, const float* d_x, int32_t batch, float* d_y,
+                            hipStream_t stream);
+
 /* Backward pass of the loss against d_target (batch x n_out FP32) for the
  * forward pass last run on d_ws with the same batch: d_grad (n_params FP32,
  * packed like the master) receives dL/dparams, d_loss (1 double) the loss.

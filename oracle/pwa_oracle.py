@@ -504,6 +504,79 @@ def grad_scale(data, mc, model, theta, v=None, chunk=100_000):
     return sg, sh
 
 
+def _hvp_abs_sums(events, model, theta, v, is_data):
+    """Per-parameter absolute sums over one event set of the pieces of the
+    per-event Hessian-vector term (theta a float array, v the direction).
+    Data events, d/d theta_p of (d ln w . v) = (H_w v)_p / w - dw_p wdot / w^2:
+        returns sum |(H_w v)_p| / w + |dw_p| |wdot| / w^2 and sum |dw_p / w|.
+    MC events: returns sum |(H_w v)_p| and sum |dw_p|.
+    Also returns the plain sum of w (G for MC)."""
+    P = theta.size
+    t = new_tag()
+    th = [Dual(float(theta[p]), float(v[p]), t) for p in range(P)]
+    kin = _kin_all(events, model)
+    z = 0
+    cols = []
+    for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
+        c = th[4 * k] + 1j * th[4 * k + 1]
+        M, G = th[4 * k + 2], th[4 * k + 3]
+        am = amplitude(kin[ch], ch, J, Dual(M, 1.0, new_tag()), G, model)
+        ag = amplitude(kin[ch], ch, J, M, Dual(G, 1.0, new_tag()), model)
+        a = am.a
+        cols += [a, 1j * a, c * am.b, c * ag.b]
+        z = z + c * a
+    zc = dconj(z)
+    w = dreal(z) * dreal(z) + dimag(z) * dimag(z)      # Dual: (w, wdot)
+    hv_abs, g_abs = np.zeros(P), np.zeros(P)
+    for p, col in enumerate(cols):
+        dw = 2.0 * dreal(zc * col)                       # Dual: (dw_p, (H_w v)_p)
+        if is_data:
+            hv_abs[p] = math.fsum(np.abs(dw.b) / w.a + np.abs(dw.a) * np.abs(w.b) / (w.a * w.a))
+            g_abs[p] = math.fsum(np.abs(dw.a) / w.a)
+        else:
+            hv_abs[p] = math.fsum(np.abs(dw.b))
+            g_abs[p] = math.fsum(np.abs(dw.a))
+    return hv_abs, g_abs, math.fsum(np.ravel(w.a))
+
+
+def hvp_scale(data, mc, model, theta, v, chunk=100_000):
+    """Rounding-error yardstick of the Hessian-vector product, eq. (7) for
+    NLL = -ln L:
+        H v = -H_F v + (N_D/G) H_G v - (N_D/G^2) dG (dG . v).
+    An FP64 evaluation that sums per-event terms makes an error of order
+    eps times the sum of the absolute values of what it adds up, so per
+    component p the scale is
+        sum_data [ |(H_w v)_p| / w + |dw_p| |wdot| / w^2 ]     (first term,
+                   both pieces of d/d theta_p of dw.v / w kept apart)
+      + (N_D/G) sum_MC |(H_w v)_p|                               (second term)
+      + 2 (N_D/G^2) A_p sum_q |v_q| A_q,  A_q = sum_MC |dw_q|    (third term:
+                   |dG_p| <= A_p and |dG . v| <= sum_q |v_q| A_q, and each
+                   factor carries its own rounding)
+    It bounds |H v| componentwise (triangle inequality) and has the units of
+    H v, so a component that cancels to ~0 is judged against it."""
+    theta = np.asarray(theta, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    P = theta.size
+    hF, hG, aG = np.zeros(P), np.zeros(P), np.zeros(P)
+    hF_parts, hG_parts, aG_parts, G_parts = [], [], [], []
+    for ev in _chunks(data, chunk):
+        if len(ev[0]):
+            hF_parts.append(_hvp_abs_sums(ev, model, theta, v, True)[0])
+    for ev in _chunks(mc, chunk):
+        if len(ev[0]):
+            h, a, g = _hvp_abs_sums(ev, model, theta, v, False)
+            hG_parts.append(h)
+            aG_parts.append(a)
+            G_parts.append(g)
+    for p in range(P):
+        hF[p] = math.fsum(x[p] for x in hF_parts)
+        hG[p] = math.fsum(x[p] for x in hG_parts)
+        aG[p] = math.fsum(x[p] for x in aG_parts)
+    G = math.fsum(G_parts)
+    nd = len(data[0])
+    return hF + (nd / G) * hG + 2.0 * (nd / (G * G)) * aG * math.fsum(np.abs(v) * aG)
+
+
 # --------------------------------------------------------------------------
 # Fixed-lineshape (batched) path: Gram matrix and per-start NLL.
 # --------------------------------------------------------------------------

@@ -94,6 +94,8 @@ SIGNATURES = {
     "pwa_mlp_cast": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, _P]),
     "pwa_mlp_forward": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, c_int32, _P, _P,
                                   c_size_t, _P]),
+    "pwa_mlp_forward_noalloc": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, c_int32, _P,
+                                          _P]),
     "pwa_mlp_backward": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, c_int32, _P, c_size_t,
                                    _P, _P, _P]),
     "pwa_mlp_adam": (c_int32, [ctypes.POINTER(PwaMlpDims), _P, _P, _P, _P, c_int32, ctypes.c_float,

@@ -1179,9 +1179,14 @@ int pwa_covariance(int32_t P, const double* H, const uint8_t* free_mask, double*
   // Cholesky factor of the free block, A = L L^T (lower triangle of L).
   std::vector<double> L((size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
-    double d = H[(size_t)idx[j] * P + idx[j]];
+    const double hjj = H[(size_t)idx[j] * P + idx[j]];
+    double d = hjj;
     for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
-    if (!(d > 0.0)) return PWA_E_DOMAIN;
+    // A pivot at or below 1e-12 n H_jj is a direction that an FP64 Hessian
+    // built from event sums does not resolve (its entries carry rounding far
+    // above n eps), e.g. the coupling phase or scale left free: its inverse
+    // would be rounding noise, so the block counts as singular.
+    if (!(d > 1e-12 * n * fabs(hjj))) return PWA_E_DOMAIN;
     const double ljj = sqrt(d);
     L[(size_t)j * n + j] = ljj;
     for (int i = j + 1; i < n; ++i) {

@@ -13,6 +13,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "pwa.h"
 #include "pwa_mlp.h"
 
@@ -315,6 +317,33 @@ hipError_t gemm(const GemmArgs& g, hipStream_t st) {
 
 inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// Device scratch of pwa_mlp_forward_noalloc: a fixed array in the library's
+// code object (each GPU holds its own copy for the life of the process).
+// Host code never uses its name as an address: the device address is looked
+// up once per device with hipGetSymbolAddress and kept here.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device (null on a HIP error).
+char* scratch_of_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+int forward_into(const pwa_mlp_dims* d, const float* w, const uint16_t* wbf, const float* x,
+                 int32_t batch, float* y, char* b, hipStream_t st);
+
 }  // namespace pwa_mlp
 
 using namespace pwa_mlp;
@@ -373,7 +402,26 @@ int pwa_mlp_forward(const pwa_mlp_dims* d, const float* w, const uint16_t* wbf, 
   if (!dims_ok(d) || !w || !wbf || !x || !y || batch < 1 || batch > 65536) return PWA_E_INVALID;
   const WsLayout L = ws_layout(d, batch);
   if (!ws || ((uintptr_t)ws % 256) != 0 || ws_bytes < L.total) return PWA_E_WORKSPACE;
-  char* b = (char*)ws;
+  return forward_into(d, w, wbf, x, batch, y, (char*)ws, st);
+}
+
+int pwa_mlp_forward_noalloc(const pwa_mlp_dims* d, const float* w, const uint16_t* wbf,
+                            const float* x, int32_t batch, float* y, hipStream_t st) {
+  if (!dims_ok(d) || !w || !wbf || !x || !y || batch < 1 || batch > 65536) return PWA_E_INVALID;
+  // the forward pass writes the buffers in front of the first backward one
+  if (ws_layout(d, batch).dy > kScratchBytes) return PWA_E_WORKSPACE;
+  char* b = scratch_of_current_device();
+  if (!b) return PWA_E_HIP;
+  return forward_into(d, w, wbf, x, batch, y, b, st);
+}
+
+}  // extern "C"
+
+namespace pwa_mlp {
+
+int forward_into(const pwa_mlp_dims* d, const float* w, const uint16_t* wbf, const float* x,
+                 int32_t batch, float* y, char* b, hipStream_t st) {
+  const WsLayout L = ws_layout(d, batch);
   const Offsets o = param_offsets(d);
   const int Bp = L.Bp;
   uint16_t *xb = (uint16_t*)(b + L.xb), *xbT = (uint16_t*)(b + L.xbT);
@@ -402,6 +450,10 @@ int pwa_mlp_forward(const pwa_mlp_dims* d, const float* w, const uint16_t* wbf, 
   if (gemm<FWD_OUT>(g, st) != hipSuccess) return PWA_E_HIP;
   return PWA_OK;
 }
+
+}  // namespace pwa_mlp
+
+extern "C" {
 
 int pwa_mlp_backward(const pwa_mlp_dims* d, const uint16_t* wtbf, const float* y, const float* t,
                      int32_t batch, void* ws, size_t ws_bytes, float* grad, double* loss,

@@ -1,12 +1,15 @@
 """Shared helpers of the GPU parity tests: seeded cases, oracle evaluation and
 the tolerance rules.
 
-Tolerances (FP64 path): the NLL to 1e-10 relative; every gradient and H v
-component to 1e-10 of its absolute-sum scale S_p = sum over events of
-|per-event term| (a rounding bound for a summed quantity is proportional to
-it; a plain relative test is meaningless where a component cancels to ~0).
+Tolerances (FP64 path): the NLL to 1e-10 relative; every gradient component
+to 1e-10 of its absolute-sum scale S_p = sum over events of |per-event term|
+(oracle.grad_scale: a rounding bound for a summed quantity is proportional to
+it; a plain relative test is meaningless where a component cancels to ~0);
+every H v component to 1e-10 of the eq. (7) scale of oracle.hvp_scale (the
+absolute sums of the three terms of eq. (7), each piece of the per-event data
+term kept apart, plus the rounding of dG and dG.v in the last term).
 FP32 path: NLL to 1e-5 relative; gradient and H v components to 3e-5 of the
-same scale (single-precision per-event arithmetic has relative error of a few
+same scales (single-precision per-event arithmetic has relative error of a few
 units of 2^-24 = 6e-8 amplified by the cancellation in M^2 - s near a pole,
 and event sums are FP64, so 3e-5 S_p bounds the sum with a wide margin).
 """
@@ -50,7 +53,8 @@ def likelihood(model, data, mc, streams=("f64",)):
 
 def oracle_all(model, data, mc, th, v):
     f, g, hv = oracle.hvp(data, mc, model, th, v)
-    S, SH = oracle.grad_scale(data, mc, model, th, v=v)
+    S = oracle.grad_scale(data, mc, model, th)
+    SH = oracle.hvp_scale(data, mc, model, th, v)
     return f, g, hv, S, SH
 
 

@@ -263,6 +263,15 @@ def test_covariance_errors(lib):
     u = np.linalg.svd(A.T)[2][-1]            # null vector of A^T
     Z = np.ascontiguousarray(A @ A.T - 1e-9 * np.outer(u, u))
     assert lib.pwa_covariance(8, ptr(Z), None, ptr(out)) == L.PWA_E_DOMAIN
+    # ... and also when rounding pushes it slightly positive: a pivot within
+    # the rounding of the elimination is a zero direction, not a tiny variance
+    for eps in (1e-15, 1e-14):
+        Zp = np.ascontiguousarray(A @ A.T + eps * np.outer(u, u))
+        assert lib.pwa_covariance(8, ptr(Zp), None, ptr(out)) == L.PWA_E_DOMAIN
+    # a genuinely ill-conditioned but positive definite block is still inverted
+    Zc = np.ascontiguousarray(A @ A.T + 1e-6 * np.outer(u, u))
+    assert lib.pwa_covariance(8, ptr(Zc), None, ptr(out)) == L.PWA_OK
+    np.testing.assert_allclose(out, np.linalg.inv(Zc), rtol=1e-6, atol=1e-6 * np.abs(out).max())
 
 
 def test_propagate():
