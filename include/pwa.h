@@ -23,9 +23,10 @@
  *     reported without touching the device.
  *
  * Physics conventions (the paper is silent on them; these are the readings):
- *   - Parent of spin 0 decaying to three distinguishable pseudoscalars with
- *     masses m[0..2]; an event is x = (s12, s13), s_ij = (p_i + p_j)^2 in
- *     GeV^2; s23 = M^2 + sum m_i^2 - s12 - s13.
+ *   - Parent of spin 0 (or 1, see pwa_bind_oriented) decaying to three
+ *     distinguishable pseudoscalars with masses m[0..2]; an event is
+ *     x = (s12, s13), s_ij = (p_i + p_j)^2 in GeV^2;
+ *     s23 = M^2 + sum m_i^2 - s12 - s13.
  *   - Channel c: 0 = (12) with bachelor 3, 1 = (13) with bachelor 2,
  *     2 = (23) with bachelor 1.  The helicity angle of channel (ab) is the
  *     angle, in the (ab) rest frame, between a and the direction opposite to
@@ -35,12 +36,16 @@
  *       Gamma_k(s) = Gamma_k (q/q0)^(2J+1) (M_k/sqrt s) [F_J(z)/F_J(z0)]^2,
  *     with q the breakup momentum, q0 = q(s = M_k^2), z = (q r)^2, and
  *     Blatt-Weisskopf F_0 = 1, F_1 = (1+z)^-1/2, F_2 = (z^2+3z+9)^-1/2.
- *     PWA_WIDTH_CONSTANT sets Gamma_k(s) = Gamma_k.
- *   - Intensity (eq. (1), one helicity term): w(x) = |sum_k c_k a_k(x)|^2.
+ *     PWA_WIDTH_CONSTANT sets Gamma_k(s) = Gamma_k.  A scalar resonance may
+ *     instead take the Flatte form (pwa_lineshape).
+ *   - Intensity (eq. (1)): w(x) = |sum_k c_k a_k(x)|^2 for a spin-0 parent
+ *     (one helicity term), sum over mu = +-1 of |sum_k c_k a_k^mu(x)|^2 for a
+ *     spin-1 parent.
  *   - NLL = -ln L = -sum_data ln w + N_D ln( (1/N_MC) sum_MC w )  (eq. (3)).
  *   - Parameter vector theta (P = 4K doubles), k-major:
  *       theta[4k+0] = Re c_k, theta[4k+1] = Im c_k,
- *       theta[4k+2] = M_k,    theta[4k+3] = Gamma_k.
+ *       theta[4k+2] = M_k,    theta[4k+3] = Gamma_k (g_1 for a Flatte
+ *       resonance).
  *   - A resonance mass at or below its pair threshold, or a non-positive
  *     intensity sum, is not an error: the NLL is +inf and a device status
  *     bit is set (read it with pwa_device_status).
@@ -83,20 +88,45 @@ typedef enum pwa_width_mode {
   PWA_WIDTH_CONSTANT = 1
 } pwa_width_mode;
 
-/* Model description (host memory, copied by pwa_create). */
+/* Lineshape of a resonance.  The paper's test model includes f0(980) in the
+ * Flatte form (Sec. 3, Table 1); the form is not written out there, and this
+ * is the reading: for a scalar (J = 0) resonance of channel (ab) with a
+ * coupled second channel of masses flatte_masses and coupling ratio
+ * r = flatte_ratio = g_2 / g_1,
+ *   a_k = 1 / (M_k^2 - s - i g_1 [rho_ab(s) + r rho_2(s)]),
+ *   rho(s) = sqrt(lambda(s, m_1^2, m_2^2)) / s  (= 2 q / sqrt s),
+ * continued below the second threshold on the physical sheet,
+ * rho_2 = +i sqrt(-lambda) / s.  theta[4k+3] is then g_1 (GeV^2) instead of
+ * Gamma_k; no barrier or angular factor (J = 0). */
+typedef enum pwa_lineshape {
+  PWA_LINESHAPE_BREIT_WIGNER = 0,
+  PWA_LINESHAPE_FLATTE = 1
+} pwa_lineshape;
+
+/* Model description (host memory, copied by pwa_create).  Zero-initialise
+ * it: the fields after `spin` default to a spin-0 parent and Breit-Wigner
+ * resonances. */
 typedef struct pwa_model {
   double parent_mass;          /* GeV                                          */
   double masses[3];            /* daughter masses m1, m2, m3 (GeV)             */
   double r;                    /* Blatt-Weisskopf radius (GeV^-1)              */
   int32_t n_res;               /* K, 1 <= K <= PWA_MAX_RES                      */
-  int32_t width_mode;          /* pwa_width_mode                               */
+  int32_t width_mode;          /* pwa_width_mode (Breit-Wigner resonances)     */
   int32_t channel[PWA_MAX_RES];/* channel of resonance k: 0, 1 or 2            */
   int32_t spin[PWA_MAX_RES];   /* spin J of resonance k: 0, 1 or 2             */
+  int32_t lineshape[PWA_MAX_RES]; /* pwa_lineshape of resonance k             */
+  double flatte_masses[2];     /* second channel of the Flatte resonances (GeV) */
+  double flatte_ratio;         /* r = g_2 / g_1 of the Flatte resonances (>= 0) */
+  int32_t parent_spin;         /* 0, or 1: a vector parent polarised along z
+                                  with mu = +1, -1 (see pwa_bind_oriented)    */
+  int32_t reserved;
 } pwa_model;
 
 typedef struct pwa_ctx pwa_ctx;
 
-/* Create a context for `model` (host memory, copied).
+/* Create a context for `model` (host memory, copied).  Models with a
+ * Flatte resonance or a spin-1 parent (the general physics path) take at
+ * most 16 resonances.
  * streams: PWA_STREAM_F64 and/or PWA_STREAM_F32 -- the event streams pwa_bind
  * will build (both are needed for mixed-precision fits).
  * Errors: PWA_E_INVALID for a null pointer, K out of range, a channel or spin
@@ -121,13 +151,40 @@ size_t pwa_workspace_bytes(const pwa_ctx* ctx, int64_t n_data, int64_t n_mc);
  * arrays are read on `stream` during this call and not retained.
  * d_ws: caller-owned device buffer of ws_bytes >= pwa_workspace_bytes(),
  * 256-byte aligned; it must stay allocated while the context is used.
- * n_data >= 0, n_mc >= 1, n_data + n_mc <= 2^29 - 64 (536 870 848) events
- * per context (larger samples are sharded over contexts and combined with
- * pwa_partials / pwa_combine).
+ * n_data >= 0, n_mc >= 1, n_data + n_mc <= 2^29 - 256 (536 870 656) events
+ * per context, or 357 000 000 with an FP32 stream (32-bit offsets within
+ * the stream planes); larger samples are sharded over contexts and combined
+ * with pwa_partials / pwa_combine.
  * Errors: PWA_E_INVALID (null pointers, sizes), PWA_E_WORKSPACE, PWA_E_HIP. */
 int pwa_bind(pwa_ctx* ctx, const double* d_s12, const double* d_s13, int64_t n_data,
              const double* d_mc_s12, const double* d_mc_s13, int64_t n_mc,
              void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* pwa_bind for a spin-1 parent (pwa_model.parent_spin = 1), whose events
+ * carry the orientation of the decay besides (s12, s13).  The paper's
+ * intensity sums the squared amplitude over the parent's helicity index mu
+ * (eq. (1): w = 1/2 sum_mu |A^mu|^2, with U_m^mu the parameter-free part);
+ * here mu = +1, -1 for a vector parent polarised along the z axis of its rest
+ * frame, and the constant 1/2 is dropped (it cancels in eq. (3)).  Reading
+ * (the paper's covariant tensors are not given): in the parent rest frame
+ * the daughters' momenta p_i lie in the plane reached from the reference
+ * plane (p_1 along x, p_2 in the upper x-y half plane) by the rotation
+ * R_y(beta) R_z(gamma); for channel (ab) with bachelor c, with p^_c the unit
+ * bachelor momentum and q^ the unit momentum of a in the (ab) rest frame
+ * (boosted along the pair's momentum), and the polarisation vectors
+ * e_+ = -(1, i, 0)/sqrt2, e_- = (1, -i, 0)/sqrt2,
+ *   U^mu = F_J(z) Y_J^mu:  Y_0 = e.p^_c,  Y_1 = e.(p^_c x q^),
+ *   Y_2 = (e.q^)(q^.p^_c) - (e.p^_c)/3,
+ * times the lineshape (parity is not imposed: the workload is synthetic).
+ * d_cosb, d_gamma: cos(beta) in [-1, 1] and gamma (radians) per event, FP64,
+ * beside the (s12, s13) arrays of each set.  Other arguments and errors as
+ * pwa_bind; pwa_bind rejects a spin-1 parent model with PWA_E_INVALID and
+ * this call a spin-0 one. */
+int pwa_bind_oriented(pwa_ctx* ctx, const double* d_s12, const double* d_s13,
+                      const double* d_cosb, const double* d_gamma, int64_t n_data,
+                      const double* d_mc_s12, const double* d_mc_s13, const double* d_mc_cosb,
+                      const double* d_mc_gamma, int64_t n_mc, void* d_ws, size_t ws_bytes,
+                      hipStream_t stream);
 
 /* Precision of subsequent pwa_nll/pwa_grad/pwa_hvp/pwa_partials calls.
  * PWA_E_INVALID if that stream was not requested at pwa_create. */
@@ -256,6 +313,21 @@ typedef struct pwa_fit_report {
 int pwa_fit(pwa_ctx* ctx, double* d_theta_inout, const pwa_fit_opts* h_opts,
             pwa_fit_report* h_rep, hipStream_t stream);
 
+/* Gradient-only comparator of pwa_fit: BFGS on the inverse Hessian (first
+ * inverse scaled by y's / y'y after the first step; no Hessian-vector
+ * products) with the same strong-Wolfe line search on the FP64 NLL and
+ * gradient; it stops when the full quasi-Newton step p, or a line-search
+ * step of at least p/2, is within the tolerance (mean |step| <= xtol).  The
+ * paper
+ * compares Newton-CG with gradient-only quasi-Newton minimisation (Migrad
+ * with AD and with finite-difference gradients, Sec. 3); this is the
+ * gradient-only arm.  Of h_opts it reads xtol, maxiter, time_cap_s and the
+ * free mask (cg_maxiter, hvp_precision, forcing, precondition are ignored);
+ * h_rep->iterations counts BFGS steps and n_hvp is 0.  Synchronous.  Errors
+ * as pwa_fit. */
+int pwa_fit_bfgs(pwa_ctx* ctx, double* d_theta_inout, const pwa_fit_opts* h_opts,
+                 pwa_fit_report* h_rep, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * At a minimum: error matrix and fit fractions.  The paper quotes a fit
  * fraction per resonance (Table 1, column F_i) without defining it; here it
@@ -327,9 +399,12 @@ int32_t pwa_n_par(const pwa_ctx* ctx);
 /* Launch shape of the NLL/gradient/HVP pass kernels (for tuning; the
  * default is an automatic choice by K).  layout 1: `groups` lanes of one
  * wavefront cooperate on each event; layout 2: `groups` wavefronts of one
- * block cooperate on each batch of 64 events.  Each lane owns `res_per_group`
- * resonances; groups * res_per_group >= K.  layout 0 restores the automatic
- * choice.  PWA_E_INVALID for a shape that is not built. */
+ * block cooperate on each batch of 64 events; layout 3: the same for models
+ * with a Flatte resonance or a spin-1 parent (the only layout those use;
+ * groups in {1, 2, 4, 8}, res_per_group 2, so K <= 16 there).  Each lane
+ * owns `res_per_group` resonances; groups * res_per_group >= K.  layout 0
+ * restores the automatic choice.  PWA_E_INVALID for a shape that is not
+ * built or does not fit the model. */
 int pwa_set_launch_shape(pwa_ctx* ctx, int32_t layout, int32_t groups, int32_t res_per_group);
 
 /* Number of thread blocks the NLL/gradient/HVP kernels launch (after

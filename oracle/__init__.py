@@ -10,5 +10,7 @@ from .pwa_oracle import (  # noqa: F401
     Dual, DomainError, new_tag, primal, kallen, kinematics, barrier, legendre,
     breakup_sq, amplitude, amplitudes, intensity, nll, partials, combine, grad,
     hvp, hessian, grad_scale, hvp_scale, gram, round_to, nll_batched, newton_cg_fit,
-    fraction_matrix, fit_fractions,
+    fraction_matrix, fit_fractions, bfgs_fit, phase_space_factor, flatte_factor, lineshape_of,
+    parent_spin, n_helicities, daughter_momenta, angular_factors, helicity_amplitudes,
 )
+from . import pwa_oracle  # noqa: F401

@@ -268,11 +268,44 @@ def legendre(J, x):
     raise ValueError("spin must be 0, 1 or 2")
 
 
-def amplitude(kin, channel, J, M, G, model):
-    """a(x) = P_J(cos) (F_J(z)/F_J(z0)) / (M^2 - s - i M Gamma(s)).
+def phase_space_factor(s, ma, mb):
+    """Two-body phase-space factor rho(s) = 2 q / sqrt(s) = sqrt(lambda(s, ma^2, mb^2)) / s,
+    continued below threshold (lambda < 0) on the physical sheet (s + i0):
+    rho = +i sqrt(-lambda) / s."""
+    lam = kallen(np.asarray(s, dtype=np.float64), ma * ma, mb * mb)
+    return np.where(lam >= 0.0, np.sqrt(np.abs(lam)) / s, 1j * np.sqrt(np.abs(lam)) / s)
+
+
+def flatte_factor(s, channel, model):
+    """The Flatte width factor rho_ab(s) + r rho_2(s) of a scalar resonance in
+    `channel` (pair a b of the daughters): rho_ab of the channel's own pair and
+    rho_2 of the coupled second channel (masses model.flatte_masses, coupling
+    ratio r = model.flatte_ratio = g_2 / g_1), complex below its threshold."""
+    a, b, _ = _PAIRS[channel]
+    m1, m2 = model.flatte_masses
+    return (phase_space_factor(s, model.masses[a], model.masses[b])
+            + model.flatte_ratio * phase_space_factor(s, m1, m2))
+
+
+def lineshape_of(model, k):
+    """0: relativistic Breit-Wigner; 1: Flatte (scalar resonances only)."""
+    ls = getattr(model, "lineshape", None)
+    return 0 if ls is None else int(ls[k])
+
+
+def amplitude(kin, channel, J, M, G, model, shape=0, angular=None):
+    """a(x) = P_J(cos) (F_J(z)/F_J(z0)) / (M^2 - s - i M Gamma(s)), or for a
+    Flatte resonance (shape 1, J = 0; G is the coupling g_1 in GeV^2)
+        a(x) = 1 / (M^2 - s - i g_1 [rho_ab(s) + r rho_2(s)]).
+    `angular` replaces P_J(cos) (a spin-1 parent's Y_J^mu).
 
     M and G may be dual numbers (for derivatives)."""
-    s, q, cos = kin
+    s, q, cos = kin[:3]
+    if shape == 1:
+        if J != 0:
+            raise ValueError("the Flatte lineshape is for scalar resonances")
+        lin = 1.0 / (M * M - s - 1j * (G * flatte_factor(s, channel, model)))
+        return lin if angular is None else angular * lin
     a, b, _ = _PAIRS[channel]
     ma, mb = model.masses[a], model.masses[b]
     r2 = model.r * model.r
@@ -285,31 +318,163 @@ def amplitude(kin, channel, J, M, G, model):
         gs = G * ipow(q / dsqrt(q0sq), 2 * J + 1) * (M / np.sqrt(s)) * (ratio * ratio)
     else:
         gs = G
-    return legendre(J, cos) * ratio / (M2 - s - 1j * (M * gs))
+    ang = legendre(J, cos) if angular is None else angular
+    return ang * ratio / (M2 - s - 1j * (M * gs))
+
+
+# --------------------------------------------------------------------------
+# Spin-1 parent (the helicity sum of eq. (1), mu = +1, -1).  Reading: events
+# carry (s12, s13, cos beta, gamma); in the parent rest frame the daughters
+# lie in the plane reached from the reference plane (p_1 along x, p_2 in the
+# upper x-y half plane) by R_y(beta) R_z(gamma).  For channel (ab) with
+# bachelor c, with p^_c the unit bachelor momentum and q^ the unit momentum
+# of a in the (ab) rest frame, and e_+ = -(1, i, 0)/sqrt2,
+# e_- = (1, -i, 0)/sqrt2:
+#   Y_0 = e.p^_c,  Y_1 = e.(p^_c x q^),  Y_2 = e_i (q^_i q^_j - delta_ij/3) p^_c_j,
+# and the amplitude's angular factor is Y_J^mu in place of P_J(cos theta).
+# --------------------------------------------------------------------------
+def parent_spin(model):
+    return int(getattr(model, "parent_spin", 0))
+
+
+def n_helicities(model):
+    return 2 if parent_spin(model) == 1 else 1
+
+
+POLARISATIONS = (np.array([-1.0, -1j, 0.0]) / math.sqrt(2.0),   # mu = +1
+                 np.array([1.0, -1j, 0.0]) / math.sqrt(2.0))    # mu = -1
+
+
+def daughter_momenta(s12, s13, cosb, gamma, model):
+    """Four-momenta (n, 3, 4) of the daughters in the parent rest frame for
+    the orientation (cos beta, gamma)."""
+    M = model.parent_mass
+    m = np.asarray(model.masses, dtype=np.float64)
+    s12 = np.asarray(s12, dtype=np.float64)
+    s13 = np.asarray(s13, dtype=np.float64)
+    s23 = M * M + np.sum(m * m) - s12 - s13
+    E = np.stack([(M * M + m[0] ** 2 - s23) / (2 * M), (M * M + m[1] ** 2 - s13) / (2 * M),
+                  (M * M + m[2] ** 2 - s12) / (2 * M)], axis=1)
+    pm = np.sqrt(np.maximum(E * E - m * m, 0.0))
+    # |p_3|^2 = |p_1 + p_2|^2 fixes the angle between p_1 and p_2
+    c12 = np.clip((pm[:, 2] ** 2 - pm[:, 0] ** 2 - pm[:, 1] ** 2) / (2 * pm[:, 0] * pm[:, 1]), -1, 1)
+    s12a = np.sqrt(1.0 - c12 * c12)
+    n = len(s12)
+    body = np.zeros((n, 3, 3))
+    body[:, 0, 0] = pm[:, 0]
+    body[:, 1, 0] = pm[:, 1] * c12
+    body[:, 1, 1] = pm[:, 1] * s12a
+    body[:, 2] = -body[:, 0] - body[:, 1]
+    cb = np.asarray(cosb, dtype=np.float64)
+    sb = np.sqrt(np.maximum(1.0 - cb * cb, 0.0))
+    g = np.asarray(gamma, dtype=np.float64)
+    Rz = np.zeros((n, 3, 3))
+    Rz[:, 0, 0], Rz[:, 0, 1], Rz[:, 1, 0], Rz[:, 1, 1], Rz[:, 2, 2] = np.cos(g), -np.sin(g), np.sin(g), np.cos(g), 1
+    Ry = np.zeros((n, 3, 3))
+    Ry[:, 0, 0], Ry[:, 0, 2], Ry[:, 1, 1], Ry[:, 2, 0], Ry[:, 2, 2] = cb, sb, 1, -sb, cb
+    R = np.einsum("nij,njk->nik", Ry, Rz)
+    lab = np.einsum("nij,ndj->ndi", R, body)
+    return np.concatenate([E[:, :, None], lab], axis=2)
+
+
+def _boost_matrix(P):
+    """Lorentz boosts (n, 4, 4) into the rest frames of four-vectors P (n, 4)."""
+    E = P[:, 0]
+    b = P[:, 1:] / E[:, None]
+    b2 = np.sum(b * b, axis=1)
+    gam = 1.0 / np.sqrt(1.0 - b2)
+    L = np.zeros((len(E), 4, 4))
+    L[:, 0, 0] = gam
+    L[:, 0, 1:] = -gam[:, None] * b
+    L[:, 1:, 0] = -gam[:, None] * b
+    with np.errstate(invalid="ignore", divide="ignore"):
+        bb = np.where(b2[:, None, None] > 0, np.einsum("ni,nj->nij", b, b) / b2[:, None, None], 0.0)
+    L[:, 1:, 1:] = np.eye(3) + (gam - 1.0)[:, None, None] * bb
+    return L
+
+
+def angular_factors(p4, channel, J):
+    """Y_J^mu (list over mu = +1, -1 of complex arrays) of channel (ab)."""
+    a, b, c = _PAIRS[channel]
+    pc = p4[:, c, 1:]
+    pch = pc / np.linalg.norm(pc, axis=1)[:, None]
+    pa_star = np.einsum("nij,nj->ni", _boost_matrix(p4[:, a] + p4[:, b]), p4[:, a])[:, 1:]
+    qh = pa_star / np.linalg.norm(pa_star, axis=1)[:, None]
+    if J == 0:
+        vec = pch
+    elif J == 1:
+        vec = np.cross(pch, qh)
+    elif J == 2:
+        T = np.einsum("ni,nj->nij", qh, qh) - np.eye(3) / 3.0
+        vec = np.einsum("nij,nj->ni", T, pch)
+    else:
+        raise ValueError("spin must be 0, 1 or 2")
+    return [vec @ e for e in POLARISATIONS]
 
 
 def _kin_all(events, model):
-    s12, s13 = events
+    s12, s13 = events[0], events[1]
     need = sorted(set(model.channel))
-    return {ch: kinematics(s12, s13, ch, model) for ch in need}
+    kin = {ch: kinematics(s12, s13, ch, model) for ch in need}
+    if parent_spin(model) == 1:
+        p4 = daughter_momenta(s12, s13, events[2], events[3], model)
+        for ch in need:
+            Js = sorted({J for c, J in zip(model.channel, model.spin) if c == ch})
+            kin[ch] = kin[ch] + ({J: angular_factors(p4, ch, J) for J in Js},)
+    return kin
+
+
+def _angular(kin_ch, J, mu, model):
+    """The angular factor of helicity term mu: P_J(cos theta) for a spin-0
+    parent (one term), Y_J^mu for a spin-1 parent."""
+    if parent_spin(model) == 0:
+        return legendre(J, kin_ch[2])
+    return kin_ch[3][J][mu]
+
+
+def helicity_amplitudes(kin, model, th, need_grad):
+    """z^mu = sum_k c_k a_k^mu for each helicity term and, with need_grad,
+    the per-parameter columns dz^mu/dtheta_p (th: floats or duals)."""
+    nmu = n_helicities(model)
+    z = [0] * nmu
+    cols = [[] for _ in range(nmu)]
+    for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
+        c = th[4 * k] + 1j * th[4 * k + 1]
+        M, G = th[4 * k + 2], th[4 * k + 3]
+        shape = lineshape_of(model, k)
+        if need_grad:
+            am = amplitude(kin[ch], ch, J, Dual(M, 1.0, new_tag()), G, model, shape, angular=1.0)
+            ag = amplitude(kin[ch], ch, J, M, Dual(G, 1.0, new_tag()), model, shape, angular=1.0)
+        for mu in range(nmu):
+            ang = _angular(kin[ch], J, mu, model)
+            if need_grad:
+                a = ang * am.a
+                # dz/dRe c = a, dz/dIm c = i a, dz/dM = c da/dM, dz/dGamma = c da/dGamma
+                cols[mu] += [a, 1j * a, c * (ang * am.b), c * (ang * ag.b)]
+            else:
+                a = amplitude(kin[ch], ch, J, M, G, model, shape, angular=ang)
+            z[mu] = z[mu] + c * a
+    return z, cols
 
 
 def amplitudes(events, model, theta):
-    """List of the K amplitude arrays a_k at the events (fixed M, Gamma)."""
+    """List of the K amplitude arrays a_k at the events (fixed M, Gamma);
+    spin-0 parent (one helicity term)."""
+    if parent_spin(model) != 0:
+        raise ValueError("one amplitude per resonance: spin-0 parent only")
     kin = _kin_all(events, model)
     out = []
     for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
-        out.append(amplitude(kin[ch], ch, J, theta[4 * k + 2], theta[4 * k + 3], model))
+        out.append(amplitude(kin[ch], ch, J, theta[4 * k + 2], theta[4 * k + 3], model,
+                             lineshape_of(model, k)))
     return out
 
 
 def intensity(events, model, theta):
-    """omega(x) = |sum_k c_k a_k(x)|^2 (eq. (1), single helicity term)."""
-    a = amplitudes(events, model, theta)
-    z = 0
-    for k, ak in enumerate(a):
-        z = z + (theta[4 * k] + 1j * theta[4 * k + 1]) * ak
-    return np.abs(z) ** 2
+    """omega(x) = sum_mu |sum_k c_k a_k^mu(x)|^2 (eq. (1); one term for a
+    spin-0 parent)."""
+    z, _ = helicity_amplitudes(_kin_all(events, model), model, [float(x) for x in theta], False)
+    return sum(np.abs(zm) ** 2 for zm in z)
 
 
 # --------------------------------------------------------------------------
@@ -322,41 +487,27 @@ def _event_sums(events, model, th, is_data, need_grad, abs_terms=False):
     Returns S (F for data, G for MC) and, if need_grad, the list of dS/dtheta_p.
     With abs_terms the per-event terms are replaced by their absolute values
     (gives the error scale sum |term|, not a derivative)."""
-    kin = _kin_all(events, model)
-    z = 0
-    cols = []
-    for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
-        c = th[4 * k] + 1j * th[4 * k + 1]
-        M, G = th[4 * k + 2], th[4 * k + 3]
-        if need_grad:
-            tm = new_tag()
-            am = amplitude(kin[ch], ch, J, Dual(M, 1.0, tm), G, model)
-            tg = new_tag()
-            ag = amplitude(kin[ch], ch, J, M, Dual(G, 1.0, tg), model)
-            a = am.a
-            # dz/dRe c = a, dz/dIm c = i a, dz/dM = c da/dM, dz/dGamma = c da/dGamma
-            cols += [a, 1j * a, c * am.b, c * ag.b]
-        else:
-            a = amplitude(kin[ch], ch, J, M, G, model)
-        z = z + c * a
-    w = dreal(z) * dreal(z) + dimag(z) * dimag(z)
+    z, cols = helicity_amplitudes(_kin_all(events, model), model, th, need_grad)
+    w = 0
+    for zm in z:
+        w = w + dreal(zm) * dreal(zm) + dimag(zm) * dimag(zm)
     term = dlog(w) if is_data else w
     S = fsum(dabs(term) if abs_terms else term)
     grads = []
     if need_grad:
-        zc = dconj(z)
-        for col in cols:
-            dw = 2.0 * dreal(zc * col)           # d omega / d theta_p
+        for p in range(len(cols[0])):
+            dw = 0
+            for zm, cm in zip(z, cols):
+                dw = dw + 2.0 * dreal(dconj(zm) * cm[p])   # d omega / d theta_p
             t = dw / w if is_data else dw
             grads.append(fsum(dabs(t) if abs_terms else t))
     return S, grads
 
 
 def _chunks(events, size):
-    s12, s13 = events
-    n = len(s12)
+    n = len(events[0])
     for i in range(0, max(n, 1), size):
-        yield s12[i:i + size], s13[i:i + size]
+        yield tuple(x[i:i + size] for x in events)
 
 
 def _sums_chunked(events, model, th, is_data, need_grad, chunk, abs_terms=False):
@@ -514,22 +665,15 @@ def _hvp_abs_sums(events, model, theta, v, is_data):
     P = theta.size
     t = new_tag()
     th = [Dual(float(theta[p]), float(v[p]), t) for p in range(P)]
-    kin = _kin_all(events, model)
-    z = 0
-    cols = []
-    for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
-        c = th[4 * k] + 1j * th[4 * k + 1]
-        M, G = th[4 * k + 2], th[4 * k + 3]
-        am = amplitude(kin[ch], ch, J, Dual(M, 1.0, new_tag()), G, model)
-        ag = amplitude(kin[ch], ch, J, M, Dual(G, 1.0, new_tag()), model)
-        a = am.a
-        cols += [a, 1j * a, c * am.b, c * ag.b]
-        z = z + c * a
-    zc = dconj(z)
-    w = dreal(z) * dreal(z) + dimag(z) * dimag(z)      # Dual: (w, wdot)
+    z, cols = helicity_amplitudes(_kin_all(events, model), model, th, True)
+    w = 0
+    for zm in z:
+        w = w + dreal(zm) * dreal(zm) + dimag(zm) * dimag(zm)   # Dual: (w, wdot)
     hv_abs, g_abs = np.zeros(P), np.zeros(P)
-    for p, col in enumerate(cols):
-        dw = 2.0 * dreal(zc * col)                       # Dual: (dw_p, (H_w v)_p)
+    for p in range(P):
+        dw = 0
+        for zm, cm in zip(z, cols):
+            dw = dw + 2.0 * dreal(dconj(zm) * cm[p])    # Dual: (dw_p, (H_w v)_p)
         if is_data:
             hv_abs[p] = math.fsum(np.abs(dw.b) / w.a + np.abs(dw.a) * np.abs(w.b) / (w.a * w.a))
             g_abs[p] = math.fsum(np.abs(dw.a) / w.a)
@@ -684,6 +828,8 @@ def fit_fractions(mc, model, theta, chunk=100_000):
     (the a-derivatives by dual numbers); then
     dF_k = dN_k / D - N_k dD / D^2.  Event sums by math.fsum per chunk, chunk
     sums by math.fsum."""
+    if parent_spin(model) != 0:
+        raise ValueError("fit fractions of one helicity term: spin-0 parent only")
     theta = np.asarray(theta, dtype=np.float64)
     K = len(model.channel)
     P = 4 * K
@@ -699,8 +845,9 @@ def fit_fractions(mc, model, theta, chunk=100_000):
         for k, (ch, J) in enumerate(zip(model.channel, model.spin)):
             c = theta[4 * k] + 1j * theta[4 * k + 1]
             M, G = theta[4 * k + 2], theta[4 * k + 3]
-            am = amplitude(kin[ch], ch, J, Dual(M, 1.0, new_tag()), G, model)
-            ag = amplitude(kin[ch], ch, J, M, Dual(G, 1.0, new_tag()), model)
+            shape = lineshape_of(model, k)
+            am = amplitude(kin[ch], ch, J, Dual(M, 1.0, new_tag()), G, model, shape)
+            ag = amplitude(kin[ch], ch, J, M, Dual(G, 1.0, new_tag()), model, shape)
             a = am.a
             y.append(c * a)
             cols.append([a, 1j * a, c * am.b, c * ag.b])
@@ -751,3 +898,31 @@ def newton_cg_fit(data, mc, model, theta0, xtol=1e-8, maxiter=200, chunk=100_000
 
     return minimize(f, np.asarray(theta0, dtype=np.float64), jac=jac, hessp=hessp,
                     method="Newton-CG", options={"xtol": xtol, "maxiter": maxiter})
+
+
+def bfgs_fit(data, mc, model, theta0, gtol=1e-5, maxiter=400, chunk=100_000):
+    """scipy.optimize.minimize(method='BFGS') on the oracle's NLL with its
+    analytic gradient: the gradient-only quasi-Newton comparator of the
+    paper's Sec. 3 (Migrad with AD gradients there)."""
+    from scipy.optimize import minimize
+
+    cache = {}
+
+    def f(th):
+        key = th.tobytes()
+        if key not in cache:
+            cache.clear()
+            try:
+                cache[key] = grad(data, mc, model, th, chunk)
+            except DomainError:
+                # a trial step with a mass below threshold: +inf, which the
+                # line search rejects (the NLL is +inf there, as in nll())
+                cache[key] = (math.inf, np.zeros(len(th)))
+        return cache[key][0]
+
+    def jac(th):
+        f(th)
+        return cache[th.tobytes()][1]
+
+    return minimize(f, np.asarray(theta0, dtype=np.float64), jac=jac, method="BFGS",
+                    options={"gtol": gtol, "maxiter": maxiter})

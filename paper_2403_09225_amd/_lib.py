@@ -24,6 +24,8 @@ PWA_PREC_F64 = 0
 PWA_PREC_F32 = 1
 PWA_STREAM_F64 = 1
 PWA_STREAM_F32 = 2
+PWA_LINESHAPE_BREIT_WIGNER = 0
+PWA_LINESHAPE_FLATTE = 1
 OPERANDS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f16x3": 4}
 
 c_double, c_int32, c_int64, c_size_t, c_void_p = (
@@ -33,7 +35,9 @@ c_double, c_int32, c_int64, c_size_t, c_void_p = (
 class PwaModel(ctypes.Structure):
     _fields_ = [("parent_mass", c_double), ("masses", c_double * 3), ("r", c_double),
                 ("n_res", c_int32), ("width_mode", c_int32),
-                ("channel", c_int32 * PWA_MAX_RES), ("spin", c_int32 * PWA_MAX_RES)]
+                ("channel", c_int32 * PWA_MAX_RES), ("spin", c_int32 * PWA_MAX_RES),
+                ("lineshape", c_int32 * PWA_MAX_RES), ("flatte_masses", c_double * 2),
+                ("flatte_ratio", c_double), ("parent_spin", c_int32), ("reserved", c_int32)]
 
 
 class PwaFitOpts(ctypes.Structure):
@@ -59,6 +63,8 @@ SIGNATURES = {
     "pwa_destroy": (None, [_P]),
     "pwa_workspace_bytes": (c_size_t, [_P, c_int64, c_int64]),
     "pwa_bind": (c_int32, [_P, _P, _P, c_int64, _P, _P, c_int64, _P, c_size_t, _P]),
+    "pwa_bind_oriented": (c_int32, [_P, _P, _P, _P, _P, c_int64, _P, _P, _P, _P, c_int64, _P,
+                                    c_size_t, _P]),
     "pwa_set_precision": (c_int32, [_P, c_int32]),
     "pwa_nll": (c_int32, [_P, _P, _P, _P]),
     "pwa_grad": (c_int32, [_P, _P, _P, _P, _P]),
@@ -69,6 +75,7 @@ SIGNATURES = {
     "pwa_intensity": (c_int32, [_P, _P, c_int32, _P, _P]),
     "pwa_combine": (c_int32, [c_int32, c_int32, _P, c_int64, c_int64, _P, _P, _P, _P, _P]),
     "pwa_fit": (c_int32, [_P, _P, ctypes.POINTER(PwaFitOpts), ctypes.POINTER(PwaFitReport), _P]),
+    "pwa_fit_bfgs": (c_int32, [_P, _P, ctypes.POINTER(PwaFitOpts), ctypes.POINTER(PwaFitReport), _P]),
     "pwa_device_status": (c_int32, [_P, _P]),
     "pwa_status_str": (ctypes.c_char_p, [c_int32]),
     "pwa_n_par": (c_int32, [_P]),

@@ -41,7 +41,12 @@ class Likelihood:
     """Unbinned PWA NLL, gradient and Hessian-vector product on one GPU."""
 
     def __init__(self, channel, spin, parent_mass=PARENT_MASS, masses=DAUGHTER_MASSES,
-                 r=R_BARRIER, width_mode=0, streams=("f64",), device="cuda"):
+                 r=R_BARRIER, width_mode=0, streams=("f64",), device="cuda", lineshape=None,
+                 flatte_masses=(0.0, 0.0), flatte_ratio=0.0, parent_spin=0):
+        """lineshape: per resonance 0 (Breit-Wigner) or 1 (Flatte, J = 0;
+        theta[4k+3] is then g_1), with the second channel's masses and the
+        coupling ratio g_2 / g_1; parent_spin 1: a vector parent (events carry
+        their orientation, see bind_oriented)."""
         self.lib = L.load()
         m = L.PwaModel()
         m.parent_mass = parent_mass
@@ -55,6 +60,11 @@ class Likelihood:
         for k, (c, j) in enumerate(zip(channel, spin)):
             m.channel[k] = int(c)
             m.spin[k] = int(j)
+            m.lineshape[k] = int(lineshape[k]) if lineshape is not None else 0
+        m.flatte_masses[0], m.flatte_masses[1] = flatte_masses
+        m.flatte_ratio = flatte_ratio
+        m.parent_spin = parent_spin
+        self.parent_spin = parent_spin
         mask = (L.PWA_STREAM_F64 if "f64" in streams else 0) | (L.PWA_STREAM_F32 if "f32" in streams else 0)
         h = ctypes.c_void_p()
         L.check("pwa_create", self.lib.pwa_create(ctypes.byref(m), mask, ctypes.byref(h)))
@@ -76,22 +86,40 @@ class Likelihood:
     def workspace_bytes(self, n_data, n_mc):
         return int(self.lib.pwa_workspace_bytes(self._h, int(n_data), int(n_mc)))
 
-    def bind(self, data_s12, data_s13, mc_s12, mc_s13):
-        """Copy events to the device (if needed) and build the event stream."""
-        d12, d13 = _dev_f64(data_s12, self.device), _dev_f64(data_s13, self.device)
-        m12, m13 = _dev_f64(mc_s12, self.device), _dev_f64(mc_s13, self.device)
-        nd, nm = int(d12.numel()), int(m12.numel())
+    def _workspace(self, nd, nm):
         nbytes = self.workspace_bytes(nd, nm)
         if nbytes == 0:
             raise ValueError("invalid event counts")
         ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-ws.data_ptr()) % 256
         self._ws = ws
-        wptr = ctypes.c_void_p(ws.data_ptr() + off)
+        return ctypes.c_void_p(ws.data_ptr() + off), nbytes
+
+    def bind(self, data_s12, data_s13, mc_s12, mc_s13):
+        """Copy events to the device (if needed) and build the event stream."""
+        d12, d13 = _dev_f64(data_s12, self.device), _dev_f64(data_s13, self.device)
+        m12, m13 = _dev_f64(mc_s12, self.device), _dev_f64(mc_s13, self.device)
+        nd, nm = int(d12.numel()), int(m12.numel())
+        wptr, nbytes = self._workspace(nd, nm)
         L.check("pwa_bind", self.lib.pwa_bind(
             self._h, _ptr(d12) if nd else None, _ptr(d13) if nd else None, nd,
             _ptr(m12), _ptr(m13), nm, wptr, nbytes, _stream()))
         torch.cuda.current_stream().synchronize()  # event arrays may be freed now
+        self.n_data, self.n_mc = nd, nm
+        return self
+
+    def bind_oriented(self, data, mc):
+        """bind for a spin-1 parent: data and mc are (s12, s13, cos_beta,
+        gamma) tuples of arrays or tensors."""
+        d = [_dev_f64(x, self.device) for x in data]
+        m = [_dev_f64(x, self.device) for x in mc]
+        nd, nm = int(d[0].numel()), int(m[0].numel())
+        wptr, nbytes = self._workspace(nd, nm)
+        dp = [_ptr(x) if nd else None for x in d]
+        L.check("pwa_bind_oriented", self.lib.pwa_bind_oriented(
+            self._h, dp[0], dp[1], dp[2], dp[3], nd, _ptr(m[0]), _ptr(m[1]), _ptr(m[2]), _ptr(m[3]),
+            nm, wptr, nbytes, _stream()))
+        torch.cuda.current_stream().synchronize()
         self.n_data, self.n_mc = nd, nm
         return self
 
@@ -101,7 +129,8 @@ class Likelihood:
 
     def set_launch_shape(self, layout=0, groups=0, res_per_group=0):
         """layout 1: `groups` lanes per event; layout 2: `groups` waves per 64
-        events; 0: automatic."""
+        events; layout 3: the same for the general physics path; 0:
+        automatic."""
         L.check("pwa_set_launch_shape",
                 self.lib.pwa_set_launch_shape(self._h, layout, groups, res_per_group))
 
@@ -269,11 +298,14 @@ class Likelihood:
 
     # ------------------------------------------------------------------- fit
     def fit(self, theta0, xtol=1e-8, maxiter=200, cg_maxiter=0, time_cap_s=0.0,
-            hvp_precision="f64", free_mask=None, forcing="scipy", precondition=False):
-        """Newton-CG fit from theta0; returns (theta, report dict).
+            hvp_precision="f64", free_mask=None, forcing="scipy", precondition=False,
+            method="newton-cg"):
+        """Newton-CG fit from theta0 (method="bfgs": the gradient-only BFGS
+        comparator, pwa_fit_bfgs); returns (theta, report dict).
         forcing: "scipy" (eta = min(1/2, sqrt(sum|g|))) or "relative"
         (eta = min(1/2, sqrt(sum|g| / sum|g_0|))).  precondition: CG with
         the inverse of |H| built from HVPs (see pwa_fit_opts)."""
+        entry = {"newton-cg": self.lib.pwa_fit, "bfgs": self.lib.pwa_fit_bfgs}[method]
         t = self._theta(theta0).clone()
         o = L.PwaFitOpts()
         o.xtol = xtol
@@ -288,9 +320,9 @@ class Likelihood:
             for i, f in enumerate(free_mask):
                 o.free_mask[i] = 1 if f else 0
         rep = L.PwaFitReport()
-        code = self.lib.pwa_fit(self._h, _ptr(t), ctypes.byref(o), ctypes.byref(rep), _stream())
+        code = entry(self._h, _ptr(t), ctypes.byref(o), ctypes.byref(rep), _stream())
         if code not in (L.PWA_OK, L.PWA_E_NOCONV, L.PWA_E_DOMAIN):
-            L.check("pwa_fit", code)
+            L.check(entry.__name__, code)
         report = {f: getattr(rep, f) for f, _ in L.PwaFitReport._fields_}
         report["code"] = int(code)
         return t, report

@@ -25,6 +25,7 @@ struct pwa_ctx {
   // bound state
   bool bound = false;
   int64_t n_data = 0, n_mc = 0, stride = 0;
+  int64_t mc_off = 0;   // first MC event of the stream: n_data rounded up to 64
   char* ws = nullptr;
   size_t ws_bytes = 0;
   int* status = nullptr;
@@ -72,9 +73,13 @@ struct pwa_ctx {
 
 namespace {
 
+// The general physics path (Flatte resonances, spin-1 parent) is built for
+// up to this many resonances (wave-group shapes G x 2, G <= 8).
+constexpr int kMaxGenRes = 16;
+
 struct Layout {
   size_t status, tbl64, tbl32, itbl, part, tot, dd, scratch, planes64, planes32, total;
-  int64_t stride;
+  int64_t stride, mc_off;
 };
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -96,7 +101,10 @@ Layout layout_of(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
   L.tot = take(sizeof(double) * 4 * (1 + NMOM_HVP * (size_t)K));
   L.dd = take(sizeof(double) * 2 * (2 + 4 * (size_t)P));
   L.scratch = take(sizeof(double) * (8 * (size_t)P + 16));
-  L.stride = (int64_t)align_up((size_t)(n_data + n_mc), 64);
+  // data events from 0, MC events from mc_off: both sets start on a
+  // 64-event boundary, so a 64-event batch is one aligned chunk per plane
+  L.mc_off = (int64_t)align_up((size_t)n_data, 64);
+  L.stride = (int64_t)align_up((size_t)(L.mc_off + n_mc), 64);
   L.planes64 = take((c->streams & PWA_STREAM_F64) ? sizeof(double) * (size_t)c->fs.n_fields * L.stride : 0);
   L.planes32 = take((c->streams & PWA_STREAM_F32) ? sizeof(float) * (size_t)c->fs.n_fields * L.stride : 0);
   L.total = off;
@@ -139,7 +147,24 @@ bool auto_nll_shape(int K, int& L, int& T, int& R) {
   return false;
 }
 
+// General physics path (layout 3): G waves of 2 resonances.
+void auto_gen_shape(int K, int& L, int& T, int& R) {
+  L = 3;
+  R = 2;
+  T = K <= 2 ? 1 : (K <= 4 ? 2 : (K <= 8 ? 4 : 8));
+}
+
 void shape_of(const pwa_ctx* c, int mode, int& L, int& T, int& R) {
+  if (c->md.gen) {
+    if (c->shape_L == 3) {
+      L = 3;
+      T = c->shape_T;
+      R = c->shape_R;
+    } else {
+      auto_gen_shape(c->K, L, T, R);
+    }
+    return;
+  }
   if (c->shape_L == 0 && mode == MODE_NLL && auto_nll_shape(c->K, L, T, R)) return;
   if (c->shape_L > 0) {
     L = c->shape_L;
@@ -155,12 +180,12 @@ int grid_blocks(pwa_ctx* c, int prec, int mode, int L, int T, int R) {
   for (const auto& g : c->grid_cache)
     if (g.prec == prec && g.mode == mode && g.L == L && g.T == T && g.R == R) cached = g.blocks;
   if (cached == 0) {
-    int occ = eval_occupancy(prec, mode, L, T, R);
+    int occ = eval_occupancy(prec, mode, L, T, R, c->fs.n_fields);
     if (occ <= 0) occ = 1;
     cached = std::max(1, std::min(MAX_BLOCKS, c->cu_count * occ));
     c->grid_cache.push_back({prec, mode, L, T, R, cached});
   }
-  const int per_iter = (L == 2) ? 64 : BLOCK / T;   // events per block per iteration
+  const int per_iter = (L >= 2) ? 64 : BLOCK / T;   // events per block per iteration
   const int64_t n = c->n_data + c->n_mc;
   const int64_t need = std::max<int64_t>(2, (n + per_iter - 1) / per_iter);
   return (int)std::min<int64_t>(cached, need);
@@ -218,6 +243,10 @@ int run_eval(pwa_ctx* c, int mode, int out_kind, int prec, const double* d_theta
   EvalArgs a;
   a.planes = prec == PWA_PREC_F32 ? (const void*)c->planes32 : (const void*)c->planes64;
   a.stride = c->stride;
+  a.n_fields = c->fs.n_fields;
+  a.mc_base = c->mc_off;
+  a.gen = c->md.gen;
+  a.nmu = c->md.parent_spin == 1 ? 2 : 1;
   a.tbl64 = c->tbl64;
   a.tbl32 = c->tbl32;
   a.itbl = c->itbl;
@@ -308,10 +337,23 @@ int pwa_create(const pwa_model* m, int32_t streams, pwa_ctx** out) {
   for (int i = 0; i < 3; ++i)
     if (!finite_pos(m->masses[i])) return PWA_E_INVALID;
   if (!(m->parent_mass > m->masses[0] + m->masses[1] + m->masses[2])) return PWA_E_INVALID;
+  if (m->parent_spin != 0 && m->parent_spin != 1) return PWA_E_INVALID;
+  bool flatte = false;
   for (int k = 0; k < m->n_res; ++k) {
     if (m->channel[k] < 0 || m->channel[k] > 2) return PWA_E_INVALID;
     if (m->spin[k] < 0 || m->spin[k] > 2) return PWA_E_INVALID;
+    if (m->lineshape[k] != PWA_LINESHAPE_BREIT_WIGNER && m->lineshape[k] != PWA_LINESHAPE_FLATTE)
+      return PWA_E_INVALID;
+    if (m->lineshape[k] == PWA_LINESHAPE_FLATTE) {
+      if (m->spin[k] != 0) return PWA_E_INVALID;   // the Flatte form is for scalars
+      flatte = true;
+    }
   }
+  if (flatte && (!finite_pos(m->flatte_masses[0]) || !finite_pos(m->flatte_masses[1]) ||
+                 !(m->flatte_ratio >= 0.0) || !isfinite(m->flatte_ratio)))
+    return PWA_E_INVALID;
+  const bool gen = flatte || m->parent_spin == 1;
+  if (gen && m->n_res > kMaxGenRes) return PWA_E_INVALID;
   pwa_ctx* c = new (std::nothrow) pwa_ctx();
   if (!c) return PWA_E_INVALID;
   c->model = *m;
@@ -320,20 +362,37 @@ int pwa_create(const pwa_model* m, int32_t streams, pwa_ctx** out) {
   c->K = m->n_res;
   c->P = 4 * m->n_res;
   // field layout: s per channel, g per (channel, J), u per (channel, J >= 1)
+  // of Breit-Wigner resonances; the general path adds the Flatte width
+  // factor per channel, a spin-1 parent's u^mu per (channel, J), and a zero
+  // plane for the factors a resonance lacks
   FieldSpec& fs = c->fs;
   for (int ch = 0; ch < 3; ++ch) {
-    fs.s_field[ch] = -1;
-    for (int J = 0; J < 3; ++J) fs.u_field[ch][J] = fs.g_field[ch][J] = -1;
+    fs.s_field[ch] = fs.fg_field[ch] = fs.fh_field[ch] = -1;
+    for (int J = 0; J < 3; ++J) {
+      fs.u_field[ch][J] = fs.g_field[ch][J] = -1;
+      for (int q = 0; q < 4; ++q) fs.uc_field[ch][J][q] = -1;
+    }
   }
   int nf = 0;
   for (int k = 0; k < c->K; ++k) {
     const int ch = m->channel[k], J = m->spin[k];
     if (fs.s_field[ch] < 0) fs.s_field[ch] = nf++;
-    if (fs.g_field[ch][J] < 0) {
+    if (m->lineshape[k] == PWA_LINESHAPE_FLATTE) {
+      if (fs.fg_field[ch] < 0) {
+        fs.fg_field[ch] = nf++;
+        fs.fh_field[ch] = nf++;
+      }
+    } else if (fs.g_field[ch][J] < 0) {
       fs.g_field[ch][J] = nf++;
-      if (J >= 1) fs.u_field[ch][J] = nf++;
+      if (J >= 1 && m->parent_spin == 0) fs.u_field[ch][J] = nf++;
+    }
+    if (m->parent_spin == 1 && fs.uc_field[ch][J][0] < 0) {
+      for (int q = 0; q < 4; ++q) fs.uc_field[ch][J][q] = nf++;
+      // the precompute writes u^mu beside the (channel, J) width factor
+      if (fs.g_field[ch][J] < 0) fs.g_field[ch][J] = nf++;
     }
   }
+  fs.zero_field = gen ? nf++ : -1;
   fs.n_fields = nf;
   ModelDev& md = c->md;
   memset(&md, 0, sizeof(md));
@@ -345,13 +404,32 @@ int pwa_create(const pwa_model* m, int32_t streams, pwa_ctx** out) {
   md.r2 = m->r * m->r;
   md.K = c->K;
   md.width_mode = m->width_mode;
+  md.parent_spin = m->parent_spin;
+  md.gen = gen ? 1 : 0;
+  md.fl_msq[0] = m->flatte_masses[0] * m->flatte_masses[0];
+  md.fl_msq[1] = m->flatte_masses[1] * m->flatte_masses[1];
+  md.fl_ratio = m->flatte_ratio;
   for (int k = 0; k < c->K; ++k) {
     const int ch = m->channel[k], J = m->spin[k];
+    const bool fl = m->lineshape[k] == PWA_LINESHAPE_FLATTE;
     md.ch[k] = ch;
     md.spin[k] = J;
-    md.fidx[k][0] = fs.s_field[ch];
-    md.fidx[k][1] = J >= 1 ? fs.u_field[ch][J] : fs.s_field[ch];
-    md.fidx[k][2] = fs.g_field[ch][J];
+    md.lineshape[k] = m->lineshape[k];
+    int* f = md.fidx[k];
+    const int zero = gen ? fs.zero_field : fs.s_field[ch];
+    f[IT_S] = fs.s_field[ch];
+    f[IT_J] = J;
+    f[IT_G] = fl ? fs.fg_field[ch] : fs.g_field[ch][J];
+    f[IT_H] = fl ? fs.fh_field[ch] : zero;
+    if (m->parent_spin == 1) {
+      f[IT_U] = fs.uc_field[ch][J][0];
+      f[IT_UI] = fs.uc_field[ch][J][1];
+      f[IT_U1R] = fs.uc_field[ch][J][2];
+      f[IT_U1I] = fs.uc_field[ch][J][3];
+    } else {
+      f[IT_U] = J >= 1 ? fs.u_field[ch][J] : fs.s_field[ch];   // J = 0: u = 1 (UMUL = 0)
+      f[IT_UI] = f[IT_U1R] = f[IT_U1I] = zero;
+    }
   }
   *out = c;
   return PWA_OK;
@@ -363,21 +441,33 @@ int32_t pwa_n_par(const pwa_ctx* c) { return c ? c->P : -1; }
 
 // Events per context: every plane of the event stream is addressed with a
 // 32-bit byte offset, so its padded length is limited to 2^32 bytes in FP64.
-constexpr int64_t kMaxEvents = ((int64_t)1 << 29) - 64;
+// Events per context: plane offsets of the stream fit 32 bits, and so do the
+// per-lane offsets of the staged loads (up to PPI - 1 planes beyond the
+// group's first: one FP64 plane, three FP32 planes).
+constexpr int64_t kMaxEvents = ((int64_t)1 << 29) - 256;
+constexpr int64_t kMaxEventsF32 = 357000000;
 
 size_t pwa_workspace_bytes(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
   if (!c || n_data < 0 || n_mc < 1) return 0;
-  if (n_data + n_mc > kMaxEvents) return 0;
+  if (n_data + n_mc > ((c->streams & PWA_STREAM_F32) ? kMaxEventsF32 : kMaxEvents)) return 0;
   return layout_of(c, n_data, n_mc).total;
 }
 
-int pwa_bind(pwa_ctx* c, const double* d_s12, const double* d_s13, int64_t n_data,
-             const double* d_mc_s12, const double* d_mc_s13, int64_t n_mc, void* d_ws,
-             size_t ws_bytes, hipStream_t st) {
+namespace {
+
+// Bind both event sets; the orientation arrays (d_cosb, d_gam and their MC
+// counterparts) are read for a spin-1 parent only.
+int bind_events(pwa_ctx* c, const double* d_s12, const double* d_s13, const double* d_cosb,
+                const double* d_gam, int64_t n_data, const double* d_mc_s12,
+                const double* d_mc_s13, const double* d_mc_cosb, const double* d_mc_gam,
+                int64_t n_mc, void* d_ws, size_t ws_bytes, hipStream_t st) {
   if (!c || n_data < 0 || n_mc < 1) return PWA_E_INVALID;
   if (n_data > 0 && (!d_s12 || !d_s13)) return PWA_E_INVALID;
   if (!d_mc_s12 || !d_mc_s13) return PWA_E_INVALID;
-  if (n_data > kMaxEvents || n_mc > kMaxEvents || n_data + n_mc > kMaxEvents) return PWA_E_INVALID;
+  if (c->md.parent_spin == 1 && ((n_data > 0 && (!d_cosb || !d_gam)) || !d_mc_cosb || !d_mc_gam))
+    return PWA_E_INVALID;
+  const int64_t max_ev = (c->streams & PWA_STREAM_F32) ? kMaxEventsF32 : kMaxEvents;
+  if (n_data > max_ev || n_mc > max_ev || n_data + n_mc > max_ev) return PWA_E_INVALID;
   if (!d_ws || ((uintptr_t)d_ws % 256) != 0) return PWA_E_WORKSPACE;
   const Layout L = layout_of(c, n_data, n_mc);
   if (ws_bytes < L.total) return PWA_E_WORKSPACE;
@@ -391,6 +481,7 @@ int pwa_bind(pwa_ctx* c, const double* d_s12, const double* d_s13, int64_t n_dat
   c->n_data = n_data;
   c->n_mc = n_mc;
   c->stride = L.stride;
+  c->mc_off = L.mc_off;
   c->ws = (char*)d_ws;
   c->ws_bytes = ws_bytes;
   c->status = (int*)(c->ws + L.status);
@@ -408,14 +499,35 @@ int pwa_bind(pwa_ctx* c, const double* d_s12, const double* d_s13, int64_t n_dat
   for (int f32 = 0; f32 < 2; ++f32) {
     void* planes = f32 ? (void*)c->planes32 : (void*)c->planes64;
     if (!planes) continue;
-    if (launch_precompute(d_s12, d_s13, n_data, 0, planes, L.stride, f32, c->md, c->fs, st) != hipSuccess)
+    if (launch_precompute(d_s12, d_s13, d_cosb, d_gam, n_data, 0, planes, L.stride, f32, c->md,
+                          c->fs, st) != hipSuccess)
       return PWA_E_HIP;
-    if (launch_precompute(d_mc_s12, d_mc_s13, n_mc, n_data, planes, L.stride, f32, c->md, c->fs, st) != hipSuccess)
+    if (launch_precompute(d_mc_s12, d_mc_s13, d_mc_cosb, d_mc_gam, n_mc, L.mc_off, planes, L.stride,
+                          f32, c->md, c->fs, st) != hipSuccess)
       return PWA_E_HIP;
   }
   c->bound = true;
   c->hvp_cache = false;
   return PWA_OK;
+}
+
+}  // namespace
+
+int pwa_bind(pwa_ctx* c, const double* d_s12, const double* d_s13, int64_t n_data,
+             const double* d_mc_s12, const double* d_mc_s13, int64_t n_mc, void* d_ws,
+             size_t ws_bytes, hipStream_t st) {
+  if (c && c->md.parent_spin != 0) return PWA_E_INVALID;
+  return bind_events(c, d_s12, d_s13, nullptr, nullptr, n_data, d_mc_s12, d_mc_s13, nullptr,
+                     nullptr, n_mc, d_ws, ws_bytes, st);
+}
+
+int pwa_bind_oriented(pwa_ctx* c, const double* d_s12, const double* d_s13, const double* d_cosb,
+                      const double* d_gam, int64_t n_data, const double* d_mc_s12,
+                      const double* d_mc_s13, const double* d_mc_cosb, const double* d_mc_gam,
+                      int64_t n_mc, void* d_ws, size_t ws_bytes, hipStream_t st) {
+  if (!c || c->md.parent_spin != 1) return PWA_E_INVALID;
+  return bind_events(c, d_s12, d_s13, d_cosb, d_gam, n_data, d_mc_s12, d_mc_s13, d_mc_cosb,
+                     d_mc_gam, n_mc, d_ws, ws_bytes, st);
 }
 
 int pwa_set_precision(pwa_ctx* c, int32_t prec) {
@@ -431,7 +543,11 @@ int pwa_set_launch_shape(pwa_ctx* c, int32_t layout, int32_t T, int32_t R) {
     c->shape_L = c->shape_T = c->shape_R = 0;
     return PWA_OK;
   }
-  const bool built = (layout == 1) ? shape_built(T, R) : (layout == 2 ? wg_shape_built(T, R) : false);
+  // layouts 1, 2 serve Breit-Wigner models of a spin-0 parent, layout 3 the
+  // general physics path
+  if ((layout == 3) != (c->md.gen != 0)) return PWA_E_INVALID;
+  const bool built = (layout == 1) ? shape_built(T, R)
+                     : (layout == 2 ? wg_shape_built(T, R) : (layout == 3 ? gen_shape_built(T, R) : false));
   if (!built || T * R < c->K || T * R > KPAD) return PWA_E_INVALID;
   c->shape_L = layout;
   c->shape_T = T;
@@ -514,13 +630,14 @@ int pwa_intensity(pwa_ctx* c, const double* d_theta, int32_t which, double* d_ou
   if (!c || !d_theta || !d_out || (which != 0 && which != 1)) return PWA_E_INVALID;
   if (!c->bound) return PWA_E_STATE;
   const int64_t n = which ? c->n_mc : c->n_data;
-  const int64_t base = which ? c->n_data : 0;
+  const int64_t base = which ? c->mc_off : 0;
   if (launch_table(d_theta, nullptr, c->md, c->K, c->tbl64, c->tbl32, c->itbl, c->status, st) !=
       hipSuccess)
     return PWA_E_HIP;
   const bool f32 = c->precision == PWA_PREC_F32;
   return launch_intensity(f32, f32 ? (const void*)c->planes32 : (const void*)c->planes64, c->stride,
-                          base, n, c->tbl64, c->itbl, c->K, d_out, st) == hipSuccess
+                          base, n, c->tbl64, c->itbl, c->K, c->md.gen,
+                          c->md.parent_spin == 1 ? 2 : 1, d_out, st) == hipSuccess
              ? PWA_OK
              : PWA_E_HIP;
 }
@@ -977,6 +1094,139 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
   return status;
 }
 
+// Gradient-only quasi-Newton comparator: BFGS on the inverse Hessian
+// approximation (Nocedal & Wright, Alg. 6.1), first inverse scaled by
+// y's/y'y after the first step (their eq. (6.20)), the same strong-Wolfe
+// search as pwa_fit, FP64 NLL and gradient only.  It stops when the full
+// quasi-Newton step, or a step of at least half of it, is within the
+// tolerance (mean |p| <= xtol).  The paper compares Newton-CG with gradient-only
+// Migrad (Sec. 3); this is that arm of the comparison in the same driver.
+int pwa_fit_bfgs(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* rep,
+                 hipStream_t st) {
+  if (!c || !d_theta || !o) return PWA_E_INVALID;
+  if (!c->bound) return PWA_E_STATE;
+  if (!(o->xtol > 0.0) || !isfinite(o->xtol)) return PWA_E_INVALID;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto elapsed = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  const int P = c->P;
+  Fitter F;
+  F.c = c;
+  F.st = st;
+  F.P = P;
+  F.free_.assign(P, 1);
+  if (o->free_mask_set)
+    for (int i = 0; i < P; ++i) F.free_[i] = o->free_mask[i] ? 1 : 0;
+  F.d_x = c->scratch;
+  F.d_v = c->scratch + P;
+  F.d_out = c->scratch + 2 * P;
+  F.prec_hvp = PWA_PREC_F64;
+  F.prec_main = (c->streams & PWA_STREAM_F64) ? PWA_PREC_F64 : PWA_PREC_F32;
+  const int maxiter = o->maxiter > 0 ? o->maxiter : 200;
+
+  std::vector<double> x(P), g;
+  if (hipMemcpyAsync(x.data(), d_theta, sizeof(double) * P, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return PWA_E_HIP;
+  double f;
+  int status = PWA_OK, converged = 0, it = 0;
+  if (!F.fg(x, f, g)) return F.err;
+  if (!isfinite(f)) status = PWA_E_DOMAIN;
+  std::vector<double> best_x = x;
+  double best_f = f;
+  // inverse Hessian approximation (row-major P x P), identity until the
+  // first curvature pair scales it
+  std::vector<double> Hi((size_t)P * P, 0.0), p(P), x1, g1, s(P), y(P), Hy(P);
+  for (int i = 0; i < P; ++i) Hi[(size_t)i * P + i] = 1.0;
+  bool scaled = false;
+  while (status == PWA_OK) {
+    if (it >= maxiter) { status = PWA_E_NOCONV; break; }
+    if (o->time_cap_s > 0 && elapsed() > o->time_cap_s) { status = PWA_E_NOCONV; break; }
+    double gmax = 0.0;
+    for (int i = 0; i < P; ++i) gmax = std::max(gmax, fabs(g[i]));
+    if (gmax == 0.0) { converged = 1; break; }
+    for (int i = 0; i < P; ++i) {
+      double a = 0.0;
+      for (int j = 0; j < P; ++j) a += Hi[(size_t)i * P + j] * g[j];
+      p[i] = -a;
+    }
+    // before any curvature is known the step is the gradient scaled to unit
+    // 2-norm (scipy's BFGS takes the same first trial length)
+    if (!scaled) {
+      const double gn = sqrt(dot(g, g));
+      for (int i = 0; i < P; ++i) p[i] *= std::min(1.0, 1.01 / gn);
+    } else if (sum_abs(p) <= P * o->xtol) {
+      // a full quasi-Newton step within the tolerance ends the fit, as a
+      // Newton step does in pwa_fit (no decrease is measurable below it)
+      converged = 1;
+      break;
+    }
+    double alpha, f1;
+    if (!wolfe(F, x, f, g, p, alpha, f1, g1, x1)) {
+      if (F.err != PWA_OK) return F.err;
+      status = PWA_E_NOCONV;
+      break;
+    }
+    double upd = 0.0;
+    for (int i = 0; i < P; ++i) {
+      s[i] = x1[i] - x[i];
+      y[i] = g1[i] - g[i];
+      upd += fabs(s[i]);
+    }
+    x = x1;
+    f = f1;
+    g = g1;
+    ++it;
+    if (f < best_f) { best_f = f; best_x = x; }
+    // the step taken ends the fit only when it was (nearly) the full
+    // quasi-Newton step: a short line-search step far from the minimum says
+    // nothing about convergence
+    if (alpha >= 0.5 && upd <= P * o->xtol) { converged = 1; break; }
+    const double ys = dot(y, s);
+    if (!(ys > 0.0)) continue;   // no curvature information: keep Hi
+    if (!scaled) {
+      const double sc = ys / dot(y, y);
+      for (int i = 0; i < P; ++i) Hi[(size_t)i * P + i] = F.free_[i] ? sc : 1.0;
+      scaled = true;
+    }
+    // Hi <- (I - rho s y') Hi (I - rho y s') + rho s s'
+    //     = Hi - rho (s (Hi y)' + (Hi y) s') + rho (1 + rho y' Hi y) s s'
+    const double rho = 1.0 / ys;
+    for (int i = 0; i < P; ++i) {
+      double a = 0.0;
+      for (int j = 0; j < P; ++j) a += Hi[(size_t)i * P + j] * y[j];
+      Hy[i] = a;
+    }
+    const double yHy = dot(y, Hy);
+    for (int i = 0; i < P; ++i)
+      for (int j = 0; j < P; ++j)
+        Hi[(size_t)i * P + j] += -rho * (s[i] * Hy[j] + Hy[i] * s[j]) + rho * (1.0 + rho * yHy) * s[i] * s[j];
+  }
+  if (status == PWA_E_DOMAIN) best_x = x;
+  if (hipMemcpyAsync(d_theta, best_x.data(), sizeof(double) * P, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return PWA_E_HIP;
+  if (rep) {
+    double gm = 0.0;
+    std::vector<double> gb;
+    double fb = best_f;
+    if (status != PWA_E_DOMAIN && F.fg(best_x, fb, gb))
+      for (int j = 0; j < P; ++j) gm = std::max(gm, fabs(gb[j]));
+    rep->nll = fb;
+    rep->grad_max = gm;
+    rep->seconds = elapsed();
+    rep->iterations = it;
+    rep->n_nll = F.n_nll;
+    rep->n_grad = F.n_grad;
+    rep->n_hvp = 0;
+    rep->status = converged ? PWA_OK : status;
+    rep->converged = converged;
+  }
+  if (converged) return PWA_OK;
+  return status;
+}
+
 // ---------------------------------------------------------------------------
 // Batched path.
 // ---------------------------------------------------------------------------
@@ -1028,6 +1278,9 @@ int pwa_freeze(pwa_ctx* c, const double* d_theta, int32_t fmt, int32_t max_batch
   if (!c || !d_theta) return PWA_E_INVALID;
   if (fmt < PWA_OP_F64 || fmt > PWA_OP_F16X3 || max_batch < 1 || max_batch > 65536) return PWA_E_INVALID;
   if (2 * c->K > kGP) return PWA_E_INVALID;
+  // one amplitude row per event: a spin-1 parent's two helicity amplitudes
+  // are not laid out on this path
+  if (c->md.parent_spin != 0) return PWA_E_INVALID;
   if (!c->bound) return PWA_E_STATE;
   if (!(c->streams & PWA_STREAM_F64)) return PWA_E_INVALID;
   if (!d_bws || ((uintptr_t)d_bws % 256) != 0) return PWA_E_WORKSPACE;
@@ -1052,10 +1305,10 @@ int pwa_freeze(pwa_ctx* c, const double* d_theta, int32_t fmt, int32_t max_batch
   // resonance table at theta (v = 0): frozen M, Gamma
   if (launch_table(d_theta, nullptr, c->md, c->K, c->tbl64, c->tbl32, c->itbl, c->status, st) != hipSuccess)
     return PWA_E_HIP;
-  if (launch_freeze(fmt, c->planes64, c->stride, c->n_data, c->tbl64, c->itbl, c->K, L.KP, c->bA_hi,
-                    c->bA_lo, st) != hipSuccess)
+  if (launch_freeze(fmt, c->planes64, c->stride, c->n_data, c->tbl64, c->itbl, c->K, L.KP,
+                    c->md.gen, c->bA_hi, c->bA_lo, st) != hipSuccess)
     return PWA_E_HIP;
-  if (launch_gram(c->planes64, c->stride, c->n_data, c->n_mc, c->tbl64, c->itbl, c->K,
+  if (launch_gram(c->planes64, c->stride, c->mc_off, c->n_mc, c->tbl64, c->itbl, c->K, c->md.gen,
                   c->bgram_blocks, c->bgram_part, c->bgram, st) != hipSuccess)
     return PWA_E_HIP;
   c->frozen = true;
@@ -1141,7 +1394,8 @@ constexpr int kPhiGramBlocks = 512;
 constexpr int kPhiGP = 48;   // padded 2K of the Gram kernel (K <= 24)
 
 size_t pwa_fraction_matrix_workspace_bytes(const pwa_ctx* c) {
-  if (!c || c->K > 24 || !(c->streams & PWA_STREAM_F64)) return 0;
+  // the MC Gram matrix holds one amplitude row per event: spin-0 parent only
+  if (!c || c->K > 24 || !(c->streams & PWA_STREAM_F64) || c->md.parent_spin != 0) return 0;
   return align_up(sizeof(double) * 2 * (size_t)kPhiGramBlocks * kPhiGP * kPhiGP, 256) +
          align_up(sizeof(double) * 2 * (size_t)c->K * c->K, 256);
 }
@@ -1160,8 +1414,8 @@ int pwa_fraction_matrix(pwa_ctx* c, const double* d_theta, void* d_ws, size_t ws
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kPhiGramBlocks, (c->n_mc + 255) / 256));
   if (launch_table(d_theta, nullptr, c->md, c->K, c->tbl64, c->tbl32, c->itbl, c->status, st) != hipSuccess)
     return PWA_E_HIP;
-  if (launch_gram(c->planes64, c->stride, c->n_data, c->n_mc, c->tbl64, c->itbl, c->K, blocks, part,
-                  gram, st) != hipSuccess)
+  if (launch_gram(c->planes64, c->stride, c->mc_off, c->n_mc, c->tbl64, c->itbl, c->K, c->md.gen,
+                  blocks, part, gram, st) != hipSuccess)
     return PWA_E_HIP;
   return launch_phi(gram, d_theta, c->K, d_phi, st) == hipSuccess ? PWA_OK : PWA_E_HIP;
 }

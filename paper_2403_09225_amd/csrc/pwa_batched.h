@@ -23,10 +23,10 @@ constexpr int kBatchChunks = 32;   // chunks of the first stage of the per-start
 int batched_kp(int fmt, int K);
 int batched_elem_bytes(int fmt);
 hipError_t launch_freeze(int fmt, const double* planes, int64_t stride, int64_t n,
-                         const double* tbl, const int* itbl, int K, int KP, void* out_hi,
+                         const double* tbl, const int* itbl, int K, int KP, int gen, void* out_hi,
                          void* out_lo, hipStream_t st);
 hipError_t launch_gram(const double* planes, int64_t stride, int64_t base, int64_t n,
-                       const double* tbl, const int* itbl, int K, int nblocks, double* part,
+                       const double* tbl, const int* itbl, int K, int gen, int nblocks, double* part,
                        double* gram, hipStream_t st);
 hipError_t launch_batched(int fmt, const BatchArgs& a, int row_blocks, const double* C,
                           const double* gram, int K, double nd, double nm, double* nll,

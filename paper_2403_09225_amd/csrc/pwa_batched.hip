@@ -102,7 +102,7 @@ template <int FMT>
 __global__ __launch_bounds__(256) void freeze_kernel(const double* __restrict__ planes, int64_t stride,
                                                      int64_t n, const double* __restrict__ tbl,
                                                      const int* __restrict__ itbl, int K, int KP,
-                                                     void* out_hi, void* out_lo) {
+                                                     int gen, void* out_hi, void* out_lo) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int c = 0; c < KP; ++c) {
@@ -113,7 +113,9 @@ __global__ __launch_bounds__(256) void freeze_kernel(const double* __restrict__ 
       const double s = planes[(int64_t)itbl[k * ITS + 0] * stride + i];
       const double u = planes[(int64_t)itbl[k * ITS + 1] * stride + i] * t[TB_UMUL] + t[TB_UADD];
       const double g = planes[(int64_t)itbl[k * ITS + 2] * stride + i];
-      const double Dr = t[TB_M2] - s, Di = t[TB_NGE] * g;
+      // Flatte resonances (general path): complex width factor g + i h
+      const double h = gen ? planes[(int64_t)itbl[k * ITS + IT_H] * stride + i] : 0.0;
+      const double Dr = t[TB_M2] - s - t[TB_NGE] * h, Di = t[TB_NGE] * g;
       const double bu = t[TB_BETA] * u * rcp64(Dr * Dr + Di * Di);
       v = (c < K) ? bu * Dr : -bu * Di;
     }
@@ -423,7 +425,7 @@ constexpr int GP = 48;   // padded 2K (K <= 24 on this path)
 __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ planes, int64_t stride,
                                                    int64_t base, int64_t n,
                                                    const double* __restrict__ tbl,
-                                                   const int* __restrict__ itbl, int K,
+                                                   const int* __restrict__ itbl, int K, int gen,
                                                    double* __restrict__ part) {
   __shared__ double X[4][16][GP];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -448,7 +450,8 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ pl
         const double s = planes[(int64_t)itbl[k * ITS + 0] * stride + x];
         const double u = planes[(int64_t)itbl[k * ITS + 1] * stride + x] * t[TB_UMUL] + t[TB_UADD];
         const double g = planes[(int64_t)itbl[k * ITS + 2] * stride + x];
-        const double Dr = t[TB_M2] - s, Di = t[TB_NGE] * g;
+        const double h = gen ? planes[(int64_t)itbl[k * ITS + IT_H] * stride + x] : 0.0;
+        const double Dr = t[TB_M2] - s - t[TB_NGE] * h, Di = t[TB_NGE] * g;
         const double bu = t[TB_BETA] * u * rcp64(Dr * Dr + Di * Di);
         re = bu * Dr;
         im = -bu * Di;
@@ -573,11 +576,11 @@ int batched_kp(int fmt, int K) {
 int batched_elem_bytes(int fmt) { return fmt == PWA_OP_F64 ? 8 : (fmt == PWA_OP_F32 ? 4 : 2); }
 
 hipError_t launch_freeze(int fmt, const double* planes, int64_t stride, int64_t n,
-                         const double* tbl, const int* itbl, int K, int KP, void* out_hi,
+                         const double* tbl, const int* itbl, int K, int KP, int gen, void* out_hi,
                          void* out_lo, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((n + 255) / 256);
-#define PWA_FZ(F) hipLaunchKernelGGL(freeze_kernel<F>, dim3(grid), dim3(256), 0, st, planes, stride, n, tbl, itbl, K, KP, out_hi, out_lo)
+#define PWA_FZ(F) hipLaunchKernelGGL(freeze_kernel<F>, dim3(grid), dim3(256), 0, st, planes, stride, n, tbl, itbl, K, KP, gen, out_hi, out_lo)
   switch (fmt) {
     case PWA_OP_F64: PWA_FZ(PWA_OP_F64); break;
     case PWA_OP_F32: PWA_FZ(PWA_OP_F32); break;
@@ -590,10 +593,10 @@ hipError_t launch_freeze(int fmt, const double* planes, int64_t stride, int64_t 
 }
 
 hipError_t launch_gram(const double* planes, int64_t stride, int64_t base, int64_t n,
-                       const double* tbl, const int* itbl, int K, int nblocks, double* part,
+                       const double* tbl, const int* itbl, int K, int gen, int nblocks, double* part,
                        double* gram, hipStream_t st) {
   hipLaunchKernelGGL(gram_kernel, dim3(nblocks), dim3(256), 0, st, planes, stride, base, n, tbl,
-                     itbl, K, part);
+                     itbl, K, gen, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gram_final_kernel, dim3(1), dim3(1024), 0, st, part, nblocks, K, gram);

@@ -58,7 +58,12 @@ enum TableSlot : int {
 constexpr int NMOM_GRAD = 6;
 constexpr int NMOM_HVP = 18;
 constexpr int TS = 32;        // table stride (reals) per resonance
-constexpr int ITS = 4;        // int table stride: s plane, u plane, g plane, J
+// Int table per resonance: plane indices of s, u, g, the spin J, and for the
+// general physics path the imaginary width factor h (Flatte) and the complex
+// angular factors of the parent's helicity amplitudes (u is the real part of
+// mu = 0; the rest are the zero plane where a model has no such factor).
+enum ITableSlot : int { IT_S = 0, IT_U = 1, IT_G = 2, IT_J = 3, IT_H = 4, IT_UI = 5, IT_U1R = 6, IT_U1I = 7 };
+constexpr int ITS = 8;
 constexpr int KPAD = 64;      // table rows (resonance slots incl. padding)
 constexpr int BLOCK = 256;    // threads per block of the evaluation kernels
 constexpr int MAX_BLOCKS = 4096;
@@ -80,9 +85,14 @@ struct ModelDev {
   double r2;                 // Blatt-Weisskopf radius^2
   int K;
   int width_mode;
+  int parent_spin;           // 0, or 1 (helicity amplitudes mu = +1, -1)
+  int gen;                   // 1: general physics path (Flatte or spin-1 parent)
+  double fl_msq[2];          // Flatte second channel: masses^2
+  double fl_ratio;           //   and coupling ratio g_2 / g_1
   int ch[PWA_MAX_RES];
   int spin[PWA_MAX_RES];
-  int fidx[PWA_MAX_RES][3];  // s, u, g plane of each resonance (u = s for J = 0)
+  int lineshape[PWA_MAX_RES];
+  int fidx[PWA_MAX_RES][ITS];  // int table row of each resonance (ITableSlot)
 };
 
 // Which planes the event stream holds.
@@ -90,16 +100,34 @@ struct FieldSpec {
   int s_field[3];            // -1: channel unused
   int u_field[3][3];         // [channel][J], -1: absent (always -1 for J = 0)
   int g_field[3][3];
+  int fg_field[3];           // Flatte width factor per channel: real part
+  int fh_field[3];           //   and imaginary part
+  int uc_field[3][3][4];     // spin-1 parent: u^mu per (channel, J): re, im of mu = +1, -1
+  int zero_field;            // a plane of zeros (general path), -1: none
   int n_fields;
 };
 
+constexpr int MAX_FIELDS = 18;   // 3 s + 6 u + 9 g planes at most
+
+// Stream staging geometry (wave-group layout): one 16-byte load per lane
+// brings 64 events of stage_ppi planes; the LDS stage buffers hold the
+// planes rounded up to whole groups of them.
+__host__ __device__ constexpr int stage_ppi(int bytes) { return 16 / bytes; }
+__host__ __device__ constexpr int stage_planes(int n_fields, int bytes) {
+  return (n_fields + stage_ppi(bytes) - 1) / stage_ppi(bytes) * stage_ppi(bytes);
+}
+
 struct EvalArgs {
   const void* planes;        // n_fields planes of `stride` reals
-  int64_t stride;
+  int64_t stride;            // a multiple of 64
+  int n_fields;
   const double* tbl64;
   const float* tbl32;
   const int* itbl;
-  int64_t n_data, n_mc;      // data events [0, n_data), MC [n_data, n_data + n_mc)
+  int64_t n_data, n_mc;      // data events [0, n_data), MC [mc_base, mc_base + n_mc)
+  int64_t mc_base;           // n_data rounded up to 64
+  int gen;                   // general physics path (wgx_kernel)
+  int nmu;                   // helicity amplitudes per event (1 or 2)
   int nb_data, nb_mc;
   int K;
   double* part;              // per-block (hi, lo) partial sums
@@ -122,12 +150,13 @@ struct FinalArgs {
 };
 
 // Launchers (pwa_kernels.hip).  All return hipError_t of the launch.
-hipError_t launch_precompute(const double* s12, const double* s13, int64_t n, int64_t offset,
-                             void* planes, int64_t stride, int is_f32, const ModelDev& md,
-                             const FieldSpec& fs, hipStream_t st);
+hipError_t launch_precompute(const double* s12, const double* s13, const double* cosb,
+                             const double* gam, int64_t n, int64_t offset, void* planes,
+                             int64_t stride, int is_f32, const ModelDev& md, const FieldSpec& fs,
+                             hipStream_t st);
 hipError_t launch_intensity(bool f32, const void* planes, int64_t stride, int64_t base, int64_t n,
-                            const double* tbl, const int* itbl, int K, double* out,
-                            hipStream_t st);
+                            const double* tbl, const int* itbl, int K, int gen, int nmu,
+                            double* out, hipStream_t st);
 hipError_t launch_table(const double* theta, const double* v, const ModelDev& md, int kslots,
                         double* tbl64, float* tbl32, int* itbl, int* status, hipStream_t st);
 // layout 1: T lanes of one wave share an event; layout 2: T waves of one
@@ -139,10 +168,11 @@ hipError_t launch_combine(int n_par, int n_shards, const double* parts, double n
                           double n_mc, const double* v, double* nll, double* grad, double* hv,
                           int* status, hipStream_t st);
 // Maximum resident blocks per CU of an evaluation kernel variant.
-int eval_occupancy(int is_f32, int mode, int layout, int T, int R);
+int eval_occupancy(int is_f32, int mode, int layout, int T, int R, int n_fields);
 // Is (T, R) an instantiated launch shape of layout 1 / layout 2?
 bool shape_built(int T, int R);
 bool wg_shape_built(int G, int R);
+bool gen_shape_built(int G, int R);
 bool nll_shape_built(int R);
 
 }  // namespace pwa

@@ -25,6 +25,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "pwa_internal.h"
 
 namespace pwa {
@@ -143,10 +145,31 @@ __device__ __forceinline__ double kallen(double x, double y, double z) {
 // For each channel in use: s of the pair; for each (channel, J) in use:
 // g = q^(2J+1) F_J(z)^2 / sqrt(s) (1 for constant width) and, for J >= 1,
 // u = F_J(z) P_J(cos th).  Computed in FP64, stored as Real.
+// General physics path: per channel with a Flatte resonance the width
+// factor rho_ab + r rho_2 (real and imaginary planes); for a spin-1 parent
+// the complex angular factors u^mu = F_J(z) Y_J^mu of mu = +1, -1 (from the
+// event's orientation: daughter momenta in the parent frame, the bachelor
+// direction and the direction of a in the pair's rest frame); a zero plane.
 // ------------------------------------------------------------------------
+struct V3 {
+  double x, y, z;
+};
+__device__ __forceinline__ V3 v3(double x, double y, double z) { return {x, y, z}; }
+__device__ __forceinline__ double dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross3(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ V3 scale3(V3 a, double k) { return {a.x * k, a.y * k, a.z * k}; }
+__device__ __forceinline__ V3 unit3(V3 a) {
+  const double n = sqrt(dot3(a, a));
+  return n > 0.0 ? scale3(a, 1.0 / n) : v3(0.0, 0.0, 0.0);
+}
+
 template <typename Real>
 __global__ __launch_bounds__(256) void precompute_kernel(const double* __restrict__ s12,
                                                          const double* __restrict__ s13,
+                                                         const double* __restrict__ cosb,
+                                                         const double* __restrict__ gam,
                                                          int64_t n, int64_t offset,
                                                          Real* __restrict__ planes,
                                                          int64_t stride, ModelDev md,
@@ -156,6 +179,34 @@ __global__ __launch_bounds__(256) void precompute_kernel(const double* __restric
   const double x12 = s12[i], x13 = s13[i];
   const double x23 = md.M2 + md.msq[0] + md.msq[1] + md.msq[2] - x12 - x13;
   const int64_t o = offset + i;
+  if (fs.zero_field >= 0) planes[fs.zero_field * stride + o] = (Real)0;
+  // spin-1 parent: daughter momenta in the parent rest frame, the decay
+  // plane rotated from the reference plane (p_1 along x, p_2 in the upper
+  // x-y half plane) by R_y(beta) R_z(gamma)
+  V3 pl[3] = {};
+  double En[3] = {};
+  if (md.parent_spin == 1) {
+    const double M = sqrt(md.M2);
+    const double sjk[3] = {x23, x13, x12};
+    double pm[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      En[d] = (md.M2 + md.msq[d] - sjk[d]) / (2.0 * M);
+      pm[d] = sqrt(fmax(En[d] * En[d] - md.msq[d], 0.0));
+    }
+    double c12 = (En[0] * En[1] - 0.5 * (x12 - md.msq[0] - md.msq[1])) / (pm[0] * pm[1]);
+    c12 = fmin(1.0, fmax(-1.0, c12));
+    const double s12n = sqrt(fmax(1.0 - c12 * c12, 0.0));
+    const V3 body[3] = {v3(pm[0], 0.0, 0.0), v3(pm[1] * c12, pm[1] * s12n, 0.0),
+                        v3(-pm[0] - pm[1] * c12, -pm[1] * s12n, 0.0)};
+    const double cb = cosb[i], sb = sqrt(fmax(1.0 - cb * cb, 0.0));
+    const double cg = cos(gam[i]), sg = sin(gam[i]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double xr = body[d].x * cg - body[d].y * sg, yr = body[d].x * sg + body[d].y * cg;
+      pl[d] = v3(xr * cb, yr, -xr * sb);
+    }
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     if (fs.s_field[c] < 0) continue;
@@ -175,6 +226,32 @@ __global__ __launch_bounds__(256) void precompute_kernel(const double* __restric
     const double cs = (sac - ma2 - mc2 - 2.0 * ea * ec) / (2.0 * q * p);
     const double z = q * q * md.r2;
     planes[fs.s_field[c] * stride + o] = (Real)sab;
+    if (fs.fg_field[c] >= 0) {
+      // Flatte width factor rho_ab + r rho_2, rho = sqrt(lambda) / s, the
+      // second channel continued below threshold to +i sqrt(-lambda) / s
+      const double lam2 = kallen(sab, md.fl_msq[0], md.fl_msq[1]);
+      const double r2re = lam2 >= 0.0 ? sqrt(lam2) / sab : 0.0;
+      const double r2im = lam2 < 0.0 ? sqrt(-lam2) / sab : 0.0;
+      planes[fs.fg_field[c] * stride + o] = (Real)(2.0 * q / rs + md.fl_ratio * r2re);
+      planes[fs.fh_field[c] * stride + o] = (Real)(md.fl_ratio * r2im);
+    }
+    // spin-1 parent: unit bachelor momentum and unit momentum of a in the
+    // (ab) rest frame (boost along the pair momentum P = -p_c)
+    V3 pc = {}, qa = {};
+    if (md.parent_spin == 1) {
+      pc = unit3(pl[cc]);
+      const V3 P = scale3(pl[cc], -1.0);
+      const double Eab = En[a] + En[b];
+      const double Pm = sqrt(dot3(P, P));
+      V3 pa = pl[a];
+      if (Pm > 0.0) {
+        const V3 Ph = scale3(P, 1.0 / Pm);
+        const double gb = Eab / rs, bb = Pm / Eab;
+        const double k = (gb - 1.0) * dot3(pa, Ph) - gb * bb * En[a];
+        pa = v3(pa.x + k * Ph.x, pa.y + k * Ph.y, pa.z + k * Ph.z);
+      }
+      qa = unit3(pa);
+    }
 #pragma unroll
     for (int J = 0; J < 3; ++J) {
       const int gf = fs.g_field[c][J];
@@ -184,9 +261,25 @@ __global__ __launch_bounds__(256) void precompute_kernel(const double* __restric
       const double qp = (J == 0) ? q : (J == 1 ? q * q2 : q * q2 * q2);   // q^(2J+1)
       const double g = (md.width_mode == PWA_WIDTH_MASS_DEPENDENT) ? qp * F2 / rs : 1.0;
       planes[gf * stride + o] = (Real)g;
-      if (J >= 1) {
+      if (J >= 1 && fs.u_field[c][J] >= 0) {
         const double PJ = (J == 1) ? cs : 1.5 * cs * cs - 0.5;
         planes[fs.u_field[c][J] * stride + o] = (Real)(sqrt(F2) * PJ);
+      }
+      if (md.parent_spin == 1 && fs.uc_field[c][J][0] >= 0) {
+        // Y_J^mu with e_+ = -(1, i, 0)/sqrt2, e_- = (1, -i, 0)/sqrt2:
+        // e_pm . v = -+(v_x +- i v_y) / sqrt2
+        V3 yv;   // Y_J = e . yv
+        if (J == 0) yv = pc;
+        else if (J == 1) yv = cross3(pc, qa);
+        else {
+          const double qp_ = dot3(qa, pc);
+          yv = v3(qa.x * qp_ - pc.x / 3.0, qa.y * qp_ - pc.y / 3.0, qa.z * qp_ - pc.z / 3.0);
+        }
+        const double f = sqrt(F2) * 0.70710678118654752440;
+        planes[fs.uc_field[c][J][0] * stride + o] = (Real)(-f * yv.x);
+        planes[fs.uc_field[c][J][1] * stride + o] = (Real)(-f * yv.y);
+        planes[fs.uc_field[c][J][2] * stride + o] = (Real)(f * yv.x);
+        planes[fs.uc_field[c][J][3] * stride + o] = (Real)(-f * yv.y);
       }
     }
   }
@@ -244,24 +337,29 @@ __global__ __launch_bounds__(64) void table_kernel(const double* __restrict__ th
       const double del = (md.m[a] - md.m[b]) * (md.m[a] - md.m[b]);
       const Jet Mj = {M, 1.0, 0.0};
       const Jet M2 = jmul(Mj, Mj);
-      // q0^2 = (M^2 - (ma+mb)^2)(M^2 - (ma-mb)^2) / (4 M^2)
-      Jet Q = jmul(jmul(jaddc(M2, -sig), jaddc(M2, -del)), jrcp(jscale(M2, 4.0)));
-      if (!(Q.v > 0.0) || !(M > 0.0) || !isfinite(Q.v)) {
-        atomicOr(&bad, 1);
-        Q = {1.0, 0.0, 0.0};
-      }
-      const Jet z0 = jscale(Q, md.r2);
-      Jet Finv2 = {1.0, 0.0, 0.0};  // 1 / F_J(z0)^2
-      if (J == 1) Finv2 = jaddc(z0, 1.0);
-      if (J == 2) Finv2 = jaddc(jadd(jmul(z0, z0), jscale(z0, 3.0)), 9.0);
-      const Jet beta = (J == 0) ? Jet{1.0, 0.0, 0.0} : jsqrt(Finv2);
-      Jet eta;
-      if (md.width_mode == PWA_WIDTH_MASS_DEPENDENT) {
-        Jet qp = jsqrt(Q);  // q0^(2J+1)
-        for (int j = 0; j < J; ++j) qp = jmul(qp, Q);
-        eta = jmul(jmul(M2, Finv2), jrcp(qp));
+      Jet beta = {1.0, 0.0, 0.0}, eta = {1.0, 0.0, 0.0};
+      if (md.lineshape[k] == PWA_LINESHAPE_FLATTE) {
+        // D = M^2 - s - i g_1 (g + i h): eta = 1, no barrier (J = 0)
+        if (!isfinite(M)) atomicOr(&bad, 1);
       } else {
-        eta = Mj;
+        // q0^2 = (M^2 - (ma+mb)^2)(M^2 - (ma-mb)^2) / (4 M^2)
+        Jet Q = jmul(jmul(jaddc(M2, -sig), jaddc(M2, -del)), jrcp(jscale(M2, 4.0)));
+        if (!(Q.v > 0.0) || !(M > 0.0) || !isfinite(Q.v)) {
+          atomicOr(&bad, 1);
+          Q = {1.0, 0.0, 0.0};
+        }
+        const Jet z0 = jscale(Q, md.r2);
+        Jet Finv2 = {1.0, 0.0, 0.0};  // 1 / F_J(z0)^2
+        if (J == 1) Finv2 = jaddc(z0, 1.0);
+        if (J == 2) Finv2 = jaddc(jadd(jmul(z0, z0), jscale(z0, 3.0)), 9.0);
+        if (J > 0) beta = jsqrt(Finv2);
+        if (md.width_mode == PWA_WIDTH_MASS_DEPENDENT) {
+          Jet qp = jsqrt(Q);  // q0^(2J+1)
+          for (int j = 0; j < J; ++j) qp = jmul(qp, Q);
+          eta = jmul(jmul(M2, Finv2), jrcp(qp));
+        } else {
+          eta = Mj;
+        }
       }
       const double Ddr = 2.0 * M * vM;
       const double Ddig = -(vM * G * eta.d + vG * eta.v);
@@ -269,8 +367,10 @@ __global__ __launch_bounds__(64) void table_kernel(const double* __restrict__ th
       const double cbr = cr * beta.v, cbi = ci * beta.v;
       e[TB_M2] = M * M;
       e[TB_NGE] = -G * eta.v;
-      e[TB_UMUL] = (J == 0) ? 0.0 : 1.0;
-      e[TB_UADD] = (J == 0) ? 1.0 : 0.0;
+      // u = u_plane UMUL + UADD: J = 0 of a spin-0 parent has u = 1
+      const bool u_one = (J == 0 && md.parent_spin == 0);
+      e[TB_UMUL] = u_one ? 0.0 : 1.0;
+      e[TB_UADD] = u_one ? 1.0 : 0.0;
       e[TB_CBR] = cbr;
       e[TB_CBI] = cbi;
       e[TB_K1R] = vr * beta.v + cr * bdot;   // cdot beta + c beta'v_M
@@ -295,15 +395,16 @@ __global__ __launch_bounds__(64) void table_kernel(const double* __restrict__ th
       e[TB_DDIG] = Ddig;
       e[TB_DMDDIG] = -(vM * G * eta.dd + vG * eta.d);
       e[TB_DGDDIG] = -vM * eta.d;
-      f[0] = md.fidx[k][0];
-      f[1] = md.fidx[k][1];
-      f[2] = md.fidx[k][2];
-      f[3] = J;
+#pragma unroll
+      for (int j = 0; j < ITS; ++j) f[j] = md.fidx[k][j];
     } else {
       // inert padding slot: c = v = 0 so it adds nothing; D = -1 - s != 0
+      // (its planes are the first resonance's, which exist)
       e[TB_M2] = -1.0;
       e[TB_UADD] = 1.0;
-      f[0] = f[1] = f[2] = f[3] = 0;
+#pragma unroll
+      for (int j = 0; j < ITS; ++j) f[j] = md.fidx[0][j];
+      f[IT_J] = 0;
     }
 #pragma unroll
     for (int j = 0; j < TS; ++j) {
@@ -322,6 +423,9 @@ __global__ __launch_bounds__(64) void table_kernel(const double* __restrict__ th
 
 // ------------------------------------------------------------------------
 // Block-range helper: blocks [0, nb_data) take data events, the rest MC.
+// Ranges start at multiples of 64 events from a set base that is itself a
+// multiple of 64, so every 64-event batch is one aligned 64-event chunk of
+// each plane (inside the plane: the stride is a multiple of 64).
 // ------------------------------------------------------------------------
 struct Range {
   bool is_data;
@@ -333,8 +437,8 @@ __device__ __forceinline__ Range block_range(const EvalArgs& a) {
   const int64_t n_set = rg.is_data ? a.n_data : a.n_mc;
   const int nb_set = rg.is_data ? a.nb_data : a.nb_mc;
   const int bi = rg.is_data ? (int)blockIdx.x : (int)blockIdx.x - a.nb_data;
-  rg.base = rg.is_data ? 0 : a.n_data;
-  const int64_t chunk = (n_set + nb_set - 1) / nb_set;
+  rg.base = rg.is_data ? 0 : a.mc_base;
+  const int64_t chunk = ((n_set + nb_set - 1) / nb_set + 63) / 64 * 64;
   rg.begin = min(n_set, (int64_t)bi * chunk);
   rg.end = min(n_set, rg.begin + chunk);
   return rg;
@@ -646,11 +750,58 @@ __global__ __launch_bounds__(BLOCK) void eval_kernel(EvalArgs a) {
 // ------------------------------------------------------------------------
 // Wave-group layout of the same pass: the G waves of a block share each batch
 // of 64 events (one event per lane) and wave g owns resonances
-// [g R, g R + R).  Table rows and plane pointers are then wave-uniform
-// (scalar registers), and the partial z, zdot of the G waves are exchanged
-// through LDS (double-buffered, one barrier per batch).  Per lane the
-// moment accumulators are those of R resonances, as in the team layout.
+// [g R, g R + R).  The block stages the stream of each batch in LDS with
+// direct global-to-LDS loads: one 16-byte load per lane brings 64 events of
+// PPI planes (2 FP64 or 4 FP32 planes), the load instructions of a batch
+// are spread over the block's waves, and so each plane chunk is read from
+// memory once per block however many of its resonances use it.  Three stage
+// buffers keep the loads of the next two batches in flight while a batch is
+// computed.  Table rows are wave-uniform (scalar registers); the partial z,
+// zdot of the G waves are exchanged through LDS (double-buffered, one
+// barrier per batch).  Per lane the moment accumulators are those of R
+// resonances, as in the team layout.
 // ------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glob_void_t;
+constexpr int NSTAGE = 3;
+
+size_t stage_lds_bytes(int n_fields, int bytes) {
+  return (size_t)NSTAGE * stage_planes(n_fields, bytes) * 64 * bytes;
+}
+
+// s_waitcnt immediate (gfx9 field layout) that waits until at most n vector
+// memory operations of this wave are in flight and leaves the other counters
+// alone; and the wave-uniform dispatch of it (immediates only).
+__host__ __device__ constexpr int vm_wait_imm(int n) {
+  return (n & 0xF) | (0x7 << 4) | (0xF << 8) | (((n >> 4) & 3) << 14);
+}
+__device__ __forceinline__ void wait_vm_at_most(int n) {
+  switch (n) {
+    case 1: __builtin_amdgcn_s_waitcnt(vm_wait_imm(1)); break;
+    case 2: __builtin_amdgcn_s_waitcnt(vm_wait_imm(2)); break;
+    case 3: __builtin_amdgcn_s_waitcnt(vm_wait_imm(3)); break;
+    case 4: __builtin_amdgcn_s_waitcnt(vm_wait_imm(4)); break;
+    case 5: __builtin_amdgcn_s_waitcnt(vm_wait_imm(5)); break;
+    case 6: __builtin_amdgcn_s_waitcnt(vm_wait_imm(6)); break;
+    case 7: __builtin_amdgcn_s_waitcnt(vm_wait_imm(7)); break;
+    case 8: __builtin_amdgcn_s_waitcnt(vm_wait_imm(8)); break;
+    case 9: __builtin_amdgcn_s_waitcnt(vm_wait_imm(9)); break;
+    default: __builtin_amdgcn_s_waitcnt(vm_wait_imm(0)); break;
+  }
+}
+
+// Block barrier over LDS written by the block's waves: this wave's LDS
+// operations are drained (lgkmcnt(0)), then s_barrier.  Unlike
+// __syncthreads it carries no memory-model fence, which would also wait for
+// the global-to-LDS loads of later batches still in flight; those are waited
+// for explicitly, one batch ahead (wait_vm_at_most).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 template <typename Real, int MODE, int G, int R>
 __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
   typedef typename CPtr<Real>::type CReal;
@@ -661,6 +812,9 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
   constexpr int NM = HVP ? NMOM_HVP : (DER ? NMOM_GRAD : 0);   // B-only: 6, as GRAD
   constexpr int NA = NM * R;
   constexpr int NX = ZD ? 4 : 2;      // exchanged reals per lane: z (, zdot)
+  constexpr int PPI = stage_ppi((int)sizeof(Real));   // planes per load instruction
+  constexpr int LPP = 64 / PPI;                       // lanes per plane
+  constexpr int JMAX = (stage_planes(MAX_FIELDS, (int)sizeof(Real)) / PPI + G - 1) / G;
 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -669,57 +823,92 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
   const int64_t stride = a.stride;
   const Real* tsrc = ((sizeof(Real) == 8) ? (const Real*)a.tbl64 : (const Real*)a.tbl32) + wv * R * TS;
 
+  // stage buffers: NSTAGE x nfp planes x 64 events (dynamic LDS)
+  extern __shared__ __attribute__((aligned(16))) char stage_lds[];
+  Real* stg = (Real*)stage_lds;
   // z and zdot exchange, double buffered: one array of (re, im) pairs per
   // quantity, so each lane's access is one contiguous pair (a 32-byte
   // per-lane stride for FP64 would conflict in the LDS banks)
   __shared__ Real xch[2][G][NX / 2][64][2];
-
-  const Real* ps[R];
-  const Real* pu[R];
-  const Real* pg[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int row = wv * R + r;
-    ps[r] = planes + (int64_t)a.itbl[row * ITS + 0] * stride;
-    pu[r] = planes + (int64_t)a.itbl[row * ITS + 1] * stride;
-    pg[r] = planes + (int64_t)a.itbl[row * ITS + 2] * stride;
-  }
 
   double accS = 0.0;
   double acc[NA > 0 ? NA : 1];
 #pragma unroll
   for (int j = 0; j < NA; ++j) acc[j] = 0.0;
 
-  if (rg.begin < rg.end) {
-    // Plane loads: wave-uniform plane base + 32-bit byte offset of the event
-    // (the stride is limited to 2^32 bytes per plane at bind time).
-    auto ld = [](const Real* base, uint32_t off) -> Real {
-      return *(const Real*)((const char*)base + off);
-    };
-    Real sc[R], uc[R], gc[R];
-    {
-      const int64_t e = rg.begin + lane;
-      const uint32_t off = (uint32_t)(rg.base + (e < rg.end ? e : rg.begin)) * (uint32_t)sizeof(Real);
+  const int nbat = (int)((rg.end - rg.begin + 63) / 64);
+  if (nbat > 0) {
+    const int nf = a.n_fields;
+    const int ni = (nf + PPI - 1) / PPI;        // load instructions per batch
+    const int nfp = ni * PPI;                   // staged planes (padded)
+    // this wave's load instructions j = wv + G jj: lane l brings 16 bytes of
+    // plane j PPI + l / LPP at event (l % LPP) PPI of the batch; in the last
+    // group, lanes past the last plane load that plane again (same
+    // addresses as its own lanes: no extra memory traffic) into padding LDS
+    // slots that are never read.  The lane's byte offset from the
+    // wave-uniform address of the group's first plane fits 32 bits (the
+    // bound on the stride is checked at bind).
+    const uint32_t pbytes = (uint32_t)(stride * (int64_t)sizeof(Real));
+    const uint32_t voff = (uint32_t)(lane / LPP) * pbytes + (uint32_t)(lane % LPP) * 16u;
+    const uint32_t voff_last = (uint32_t)min(lane / LPP, nf - 1 - (ni - 1) * PPI) * pbytes +
+                               (uint32_t)(lane % LPP) * 16u;
+    const Real* bsrc = planes + rg.base + rg.begin;
+    int nmine = 0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        sc[r] = ld(ps[r], off);
-        uc[r] = ld(pu[r], off);
-        gc[r] = ld(pg[r], off);
+    for (int jj = 0; jj < JMAX; ++jj) nmine += (wv + G * jj < ni) ? 1 : 0;
+    // batch b (clamped to the last one: loads past the range refetch it)
+    // into stage buffer `stage`
+    auto issue = [&](int b, int stage) {
+      const int64_t off = (int64_t)min(b, nbat - 1) * 64;
+#pragma unroll
+      for (int jj = 0; jj < JMAX; ++jj) {
+        const int j = wv + G * jj;
+        if (j < ni) {
+          const char* base = (const char*)(bsrc + (int64_t)j * PPI * stride + off);
+          __builtin_amdgcn_global_load_lds((glob_void_t*)(base + (j == ni - 1 ? voff_last : voff)),
+                                           (lds_void_t*)(stg + (stage * nfp + j * PPI) * 64), 16, 0, 0);
+        }
       }
-    }
-    int buf = 0;
-    for (int64_t e0 = rg.begin; e0 < rg.end; e0 += 64, buf ^= 1) {
-      const bool valid = e0 + lane < rg.end;
-      Real sn[R], un[R], gn[R];
+    };
+    // LDS offsets (reals) of this wave's (s, u, g) planes
+    int fo[R][3];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) fo[r][k] = a.itbl[(wv * R + r) * ITS + k] * 64;
+
+    issue(0, 0);
+    issue(1, 1);
+    wait_vm_at_most(nmine);   // this wave's loads of batch 0 are in LDS
+    lds_barrier();            // and so are every wave's
+    int stage = 0, buf = 0;
+    // One batch.  LAST: the block's last batch, the only one whose lanes can
+    // lie past the range (a separate instance, so the others carry no
+    // per-lane masking).
+    auto step = [&](const int b, auto last_tag) {
+      constexpr bool LAST = decltype(last_tag)::value;
+      // ---- this batch's stream values, then the refill two batches ahead
+      // (the buffer read one batch ago, which every wave has finished with:
+      // all passed the last barrier after reading it)
+      Real sc[R], uc[R], gc[R];
       {
-        const int64_t en = e0 + 64 + lane;
-        const uint32_t off = (uint32_t)(rg.base + (en < rg.end ? en : rg.begin)) * (uint32_t)sizeof(Real);
+        const Real* sb = stg + stage * nfp * 64 + lane;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          sn[r] = ld(ps[r], off);
-          un[r] = ld(pu[r], off);
-          gn[r] = ld(pg[r], off);
+          sc[r] = sb[fo[r][0]];
+          uc[r] = sb[fo[r][1]];
+          gc[r] = sb[fo[r][2]];
         }
+      }
+      asm volatile("" ::: "memory");
+      issue(b + 2, stage == 0 ? 2 : stage - 1);
+      const int64_t e0 = rg.begin + (int64_t)b * 64;
+      if (LAST && !(e0 + lane < rg.end)) {
+        // lanes past the range (last batch only) may hold the unwritten
+        // padding between the data and MC sets: give them finite values
+        // (D = M^2 - 0 is nonzero), their contributions are zeroed below
+#pragma unroll
+        for (int r = 0; r < R; ++r) sc[r] = uc[r] = gc[r] = 0;
       }
       CReal* tb = opaque_s((CReal*)tsrc);
 
@@ -761,20 +950,32 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
         const Real g = gc[r];
         const Real wr = Dr_[r] * inv_[r], wi = -Di_[r] * inv_[r];
         const Real uwr = u * wr, uwi = u * wi;
-        zr = fma_r(t[TB_CBR], uwr, fma_r(-t[TB_CBI], uwi, zr));
-        zi = fma_r(t[TB_CBR], uwi, fma_r(t[TB_CBI], uwr, zi));
+        if (r == 0) {
+          zr = fma_r(t[TB_CBR], uwr, -t[TB_CBI] * uwi);
+          zi = fma_r(t[TB_CBR], uwi, t[TB_CBI] * uwr);
+        } else {
+          zr = fma_r(t[TB_CBR], uwr, fma_r(-t[TB_CBI], uwi, zr));
+          zi = fma_r(t[TB_CBR], uwi, fma_r(t[TB_CBI], uwr, zi));
+        }
         if constexpr (ZD) {
           const Real uw2r = uwr * wr - uwi * wi, uw2i = uwr * wi + uwi * wr;
           const Real kr = mad_nc(t[TB_K3R], g, t[TB_K2R]);
           const Real ki = mad_nc(t[TB_K3I], g, t[TB_K2I]);
-          zdr = fma_r(t[TB_K1R], uwr, fma_r(-t[TB_K1I], uwi, fma_r(kr, uw2r, fma_r(-ki, uw2i, zdr))));
-          zdi = fma_r(t[TB_K1R], uwi, fma_r(t[TB_K1I], uwr, fma_r(kr, uw2i, fma_r(ki, uw2r, zdi))));
+          if (r == 0) {
+            zdr = fma_r(t[TB_K1R], uwr, fma_r(-t[TB_K1I], uwi, fma_r(kr, uw2r, -ki * uw2i)));
+            zdi = fma_r(t[TB_K1R], uwi, fma_r(t[TB_K1I], uwr, fma_r(kr, uw2i, ki * uw2r)));
+          } else {
+            zdr = fma_r(t[TB_K1R], uwr, fma_r(-t[TB_K1I], uwi, fma_r(kr, uw2r, fma_r(-ki, uw2i, zdr))));
+            zdi = fma_r(t[TB_K1R], uwi, fma_r(t[TB_K1I], uwr, fma_r(kr, uw2i, fma_r(ki, uw2r, zdi))));
+          }
         }
         cwr[r] = wr;
         cwi[r] = wi;
         cu[r] = u;
       }
-      // ---- exchange: every wave sums the G shares in group order
+      // ---- exchange: every wave sums the G shares in group order.  Before
+      // the barrier each wave also waits for its own loads of the next
+      // batch, so that after it the whole next batch is in LDS.
       if constexpr (G > 1) {
         xch[buf][wv][0][lane][0] = zr;
         xch[buf][wv][0][lane][1] = zi;
@@ -782,10 +983,20 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
           xch[buf][wv][1][lane][0] = zdr;
           xch[buf][wv][1][lane][1] = zdi;
         }
-        __syncthreads();
-        zr = zi = zdr = zdi = 0;
+      }
+      wait_vm_at_most(nmine);
+      lds_barrier();
+      if constexpr (G > 1) {
+        zr = xch[buf][0][0][lane][0];
+        zi = xch[buf][0][0][lane][1];
+        if constexpr (ZD) {
+          zdr = xch[buf][0][1][lane][0];
+          zdi = xch[buf][0][1][lane][1];
+        }
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 1; g < G; ++g) {
+          // one share at a time (keeps the exchange's registers few)
+          asm volatile("" ::: "memory");
           zr += xch[buf][g][0][lane][0];
           zi += xch[buf][g][0][lane][1];
           if constexpr (ZD) {
@@ -795,12 +1006,12 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
         }
       }
 
-      // ---- per-event weights
+      // ---- per-event weights (the data log is taken after pass 2, where
+      // fewer registers are live)
       const Real om = zr * zr + zi * zi;
       Real gr = 0, gi = 0, alr = 0, ali = 0;
       double sterm = 0.0;
       if (rg.is_data) {
-        if (!BON && wv == 0) sterm = (double)log_r(om);
         if constexpr (DER) {
           const Real io = rcp_r(om);
           gr = zr * io;
@@ -818,11 +1029,9 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
         alr = zdr;
         ali = -zdi;
       }
-      if (!valid) {
-        sterm = 0.0;
-        gr = gi = alr = ali = 0;
-      }
-      if (wv == 0) accS += sterm;
+      // only the last batch of a block can hold events past its range
+      const bool dead = LAST && !(e0 + lane < rg.end);
+      if (dead) gr = gi = alr = ali = 0;
 
       // ---- pass 2: moments (chain p = x u w, q = p w, r = q w)
       if constexpr (BON) {
@@ -845,6 +1054,9 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
       } else if constexpr (DER) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+          // one resonance at a time: the scheduler may not interleave the
+          // resonances' products (their temporaries would cost occupancy)
+          __builtin_amdgcn_sched_barrier(0);
           const Real wr = cwr[r], wi = cwi[r], g = gc[r];
           const Real uwr = cu[r] * wr, uwi = cu[r] * wi;
           double* m = acc + NM * r;
@@ -876,17 +1088,256 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
           }
         }
       }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        sc[r] = sn[r];
-        uc[r] = un[r];
-        gc[r] = gn[r];
+      if (!BON && wv == 0) {
+        if (rg.is_data) sterm = (double)log_r(om);
+        accS += dead ? 0.0 : sterm;
       }
-    }
+      stage = (stage == NSTAGE - 1) ? 0 : stage + 1;
+      buf ^= 1;
+    };
+    for (int b = 0; b < nbat - 1; ++b) step(b, std::false_type{});
+    step(nbat - 1, std::true_type{});
   }
 
   // ---- reduction: each wave owns its resonances, so a wave-level
   // butterfly (fixed order, symmetric) gives the block partial directly.
+  const int K = a.K;
+  const int V = 1 + NM * K;
+  double* out = a.part + (int64_t)blockIdx.x * V * 2;
+  if (wv == 0) {
+    double hi = accS, lo = 0.0;
+    dd_wave_reduce(hi, lo, 1);
+    if (lane == 0) {
+      out[0] = hi;
+      out[1] = lo;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    double x = acc[j];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) x += __shfl_xor(x, off);
+    const int k = wv * R + j / NM;
+    if (lane == 0 && k < K) {
+      out[(1 + NM * k + j % NM) * 2] = x;
+      out[(1 + NM * k + j % NM) * 2 + 1] = 0.0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// General physics path of the same pass (any Flatte resonance, or a spin-1
+// parent).  Per resonance the width factor is complex, g + i h (h = 0 for a
+// Breit-Wigner), so D = (M^2 - s - NGE h) + i NGE g, and each event carries
+// nmu = 1 or 2 helicity amplitudes z^mu = sum_k c_k beta_k u_k^mu w_k with
+// complex u^mu (eq. (1): w = sum_mu |z^mu|^2).  The moments keep their form
+// with gamma u and alpha u replaced by P = sum_mu gamma^mu u^mu and
+// Q = sum_mu alpha^mu u^mu, and g by the complex g + i h, so the finaliser
+// is shared.  Wave-group layout as wg_kernel (G waves x R resonances, z^mu
+// and zdot^mu exchanged through LDS); stream values are loaded straight
+// into registers (this path favours generality over the last factor of
+// speed).
+// ------------------------------------------------------------------------
+template <typename Real, int MODE, int G, int R>
+__global__ __launch_bounds__(64 * G) void wgx_kernel(EvalArgs a) {
+  typedef typename CPtr<Real>::type CReal;
+  constexpr bool HVP = (MODE == MODE_HVP);
+  constexpr bool BON = (MODE == MODE_HVPB);
+  constexpr bool ZD = HVP || BON;
+  constexpr bool DER = (MODE != MODE_NLL);
+  constexpr int NM = HVP ? NMOM_HVP : (DER ? NMOM_GRAD : 0);
+  constexpr int NA = NM * R;
+  constexpr int NQ = ZD ? 2 : 1;      // exchanged complex values per mu: z (, zdot)
+
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const Range rg = block_range(a);
+  const Real* __restrict__ planes = (const Real*)a.planes;
+  const int64_t stride = a.stride;
+  const int nmu = a.nmu;
+  const Real* tsrc = ((sizeof(Real) == 8) ? (const Real*)a.tbl64 : (const Real*)a.tbl32) + wv * R * TS;
+  __shared__ Real xch[2][G][2][NQ][64][2];
+
+  // plane bases of this wave's resonances: s, g, h, u^0 (re, im), u^1 (re, im)
+  const Real* pb[R][7];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int* it = a.itbl + (wv * R + r) * ITS;
+    const int sl[7] = {IT_S, IT_G, IT_H, IT_U, IT_UI, IT_U1R, IT_U1I};
+#pragma unroll
+    for (int f = 0; f < 7; ++f) pb[r][f] = planes + (int64_t)it[sl[f]] * stride;
+  }
+
+  double accS = 0.0;
+  double acc[NA > 0 ? NA : 1];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+
+  int buf = 0;
+  for (int64_t e0 = rg.begin; e0 < rg.end; e0 += 64, buf ^= 1) {
+    const bool valid = e0 + lane < rg.end;
+    const int64_t ev = rg.base + (valid ? e0 + lane : rg.begin);
+    CReal* tb = opaque_s((CReal*)tsrc);
+    // ---- pass 1: w, u^mu of each resonance; this wave's share of z^mu, zdot^mu
+    Real wr_[R], wi_[R], g_[R], h_[R], ur_[R][2], ui_[R][2];
+    Real zr[2] = {0, 0}, zi[2] = {0, 0}, zdr[2] = {0, 0}, zdi[2] = {0, 0};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      CReal* t = tb + r * TS;
+      const Real sv = pb[r][0][ev];
+      g_[r] = pb[r][1][ev];
+      h_[r] = pb[r][2][ev];
+      const Real Dr = t[TB_M2] - sv - t[TB_NGE] * h_[r];
+      const Real Di = t[TB_NGE] * g_[r];
+      const Real inv = rcp_r(Dr * Dr + Di * Di);
+      wr_[r] = Dr * inv;
+      wi_[r] = -Di * inv;
+      // zdot coefficient K2 + K3 (g + i h)
+      const Real kr = t[TB_K2R] + t[TB_K3R] * g_[r] - t[TB_K3I] * h_[r];
+      const Real ki = t[TB_K2I] + t[TB_K3R] * h_[r] + t[TB_K3I] * g_[r];
+#pragma unroll
+      for (int mu = 0; mu < 2; ++mu) {
+        if (mu >= nmu) break;
+        const Real urr = mu == 0 ? mad_nc(pb[r][3][ev], t[TB_UMUL], t[TB_UADD]) : pb[r][5][ev];
+        const Real uii = mu == 0 ? pb[r][4][ev] : pb[r][6][ev];
+        ur_[r][mu] = urr;
+        ui_[r][mu] = uii;
+        const Real Ur = urr * wr_[r] - uii * wi_[r], Ui = urr * wi_[r] + uii * wr_[r];
+        zr[mu] += t[TB_CBR] * Ur - t[TB_CBI] * Ui;
+        zi[mu] += t[TB_CBR] * Ui + t[TB_CBI] * Ur;
+        if constexpr (ZD) {
+          const Real Uwr = Ur * wr_[r] - Ui * wi_[r], Uwi = Ur * wi_[r] + Ui * wr_[r];
+          zdr[mu] += t[TB_K1R] * Ur - t[TB_K1I] * Ui + kr * Uwr - ki * Uwi;
+          zdi[mu] += t[TB_K1R] * Ui + t[TB_K1I] * Ur + kr * Uwi + ki * Uwr;
+        }
+      }
+    }
+    // ---- exchange
+    if constexpr (G > 1) {
+#pragma unroll
+      for (int mu = 0; mu < 2; ++mu) {
+        if (mu >= nmu) break;
+        xch[buf][wv][mu][0][lane][0] = zr[mu];
+        xch[buf][wv][mu][0][lane][1] = zi[mu];
+        if constexpr (ZD) {
+          xch[buf][wv][mu][NQ - 1][lane][0] = zdr[mu];
+          xch[buf][wv][mu][NQ - 1][lane][1] = zdi[mu];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int mu = 0; mu < 2; ++mu) {
+        if (mu >= nmu) break;
+        zr[mu] = zi[mu] = zdr[mu] = zdi[mu] = 0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          zr[mu] += xch[buf][g][mu][0][lane][0];
+          zi[mu] += xch[buf][g][mu][0][lane][1];
+          if constexpr (ZD) {
+            zdr[mu] += xch[buf][g][mu][NQ - 1][lane][0];
+            zdi[mu] += xch[buf][g][mu][NQ - 1][lane][1];
+          }
+        }
+      }
+    }
+    // ---- per-event weights gamma^mu, alpha^mu
+    Real om = 0, od = 0;
+#pragma unroll
+    for (int mu = 0; mu < 2; ++mu) {
+      if (mu >= nmu) break;
+      om += zr[mu] * zr[mu] + zi[mu] * zi[mu];
+      od += zr[mu] * zdr[mu] + zi[mu] * zdi[mu];
+    }
+    Real gr[2] = {0, 0}, gi[2] = {0, 0}, alr[2] = {0, 0}, ali[2] = {0, 0};
+    double sterm = 0.0;
+    if (rg.is_data) {
+      if (!BON && wv == 0) sterm = (double)log_r(om);
+      if constexpr (DER) {
+        const Real io = rcp_r(om);
+        const Real tt = 2 * od * io;
+#pragma unroll
+        for (int mu = 0; mu < 2; ++mu) {
+          gr[mu] = zr[mu] * io;
+          gi[mu] = -zi[mu] * io;
+          if constexpr (ZD) {
+            alr[mu] = (zdr[mu] - tt * zr[mu]) * io;
+            ali[mu] = (tt * zi[mu] - zdi[mu]) * io;
+          }
+        }
+      }
+    } else {
+      if (!BON) sterm = (double)om;
+#pragma unroll
+      for (int mu = 0; mu < 2; ++mu) {
+        gr[mu] = zr[mu];
+        gi[mu] = -zi[mu];
+        alr[mu] = zdr[mu];
+        ali[mu] = -zdi[mu];
+      }
+    }
+    if (!valid) {
+      sterm = 0.0;
+#pragma unroll
+      for (int mu = 0; mu < 2; ++mu) gr[mu] = gi[mu] = alr[mu] = ali[mu] = 0;
+    }
+    if (wv == 0) accS += sterm;
+    // ---- pass 2: P = sum gamma^mu u^mu, Q = sum alpha^mu u^mu, chain
+    // p = P w, q = p w, r = q w (a = Q w, b = a w); complex g + i h
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const Real wr = wr_[r], wi = wi_[r], g = g_[r], hh = h_[r];
+      Real Pr = 0, Pi = 0, Qr = 0, Qi = 0;
+#pragma unroll
+      for (int mu = 0; mu < 2; ++mu) {
+        if (mu >= nmu) break;
+        const Real ur = ur_[r][mu], ui = ui_[r][mu];
+        Pr += gr[mu] * ur - gi[mu] * ui;
+        Pi += gr[mu] * ui + gi[mu] * ur;
+        Qr += alr[mu] * ur - ali[mu] * ui;
+        Qi += alr[mu] * ui + ali[mu] * ur;
+      }
+      double* m = acc + NM * r;
+      if constexpr (BON) {
+        const Real ar_ = Qr * wr - Qi * wi, ai_ = Qr * wi + Qi * wr;
+        const Real br_ = ar_ * wr - ai_ * wi, bi_ = ar_ * wi + ai_ * wr;
+        acc_add(m[0], ar_);
+        acc_add(m[1], ai_);
+        acc_add(m[2], br_);
+        acc_add(m[3], bi_);
+        acc_add(m[4], g * br_ - hh * bi_);
+        acc_add(m[5], g * bi_ + hh * br_);
+      } else if constexpr (DER) {
+        const Real pr = Pr * wr - Pi * wi, pi = Pr * wi + Pi * wr;
+        const Real qr = pr * wr - pi * wi, qi = pr * wi + pi * wr;
+        acc_add(m[0], pr);
+        acc_add(m[1], pi);
+        acc_add(m[2], qr);
+        acc_add(m[3], qi);
+        acc_add(m[4], g * qr - hh * qi);
+        acc_add(m[5], g * qi + hh * qr);
+        if constexpr (HVP) {
+          const Real ar_ = Qr * wr - Qi * wi, ai_ = Qr * wi + Qi * wr;
+          const Real br_ = ar_ * wr - ai_ * wi, bi_ = ar_ * wi + ai_ * wr;
+          acc_add(m[6], ar_);
+          acc_add(m[7], ai_);
+          acc_add(m[8], br_);
+          acc_add(m[9], bi_);
+          acc_add(m[10], g * br_ - hh * bi_);
+          acc_add(m[11], g * bi_ + hh * br_);
+          const Real rr = qr * wr - qi * wi, ri = qr * wi + qi * wr;
+          const Real g2r = g * g - hh * hh, g2i = 2 * g * hh;
+          acc_add(m[12], rr);
+          acc_add(m[13], ri);
+          acc_add(m[14], g * rr - hh * ri);
+          acc_add(m[15], g * ri + hh * rr);
+          acc_add(m[16], g2r * rr - g2i * ri);
+          acc_add(m[17], g2r * ri + g2i * rr);
+        }
+      }
+    }
+  }
+
+  // ---- reduction (as wg_kernel)
   const int K = a.K;
   const int V = 1 + NM * K;
   double* out = a.part + (int64_t)blockIdx.x * V * 2;
@@ -1165,53 +1616,65 @@ __global__ __launch_bounds__(256) void intensity_kernel(const Real* __restrict__
                                                         int64_t stride, int64_t base, int64_t n,
                                                         const double* __restrict__ tbl,
                                                         const int* __restrict__ itbl, int K,
+                                                        int gen, int nmu,
                                                         double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t e = base + i;
-  double zr = 0.0, zi = 0.0;
+  auto at = [&](int k, int slot) -> double {
+    return (double)planes[(int64_t)itbl[k * ITS + slot] * stride + e];
+  };
+  double zr[2] = {0.0, 0.0}, zi[2] = {0.0, 0.0};
   for (int k = 0; k < K; ++k) {
     const double* t = tbl + k * TS;
-    const double s = (double)planes[(int64_t)itbl[k * ITS + 0] * stride + e];
-    const double u = (double)planes[(int64_t)itbl[k * ITS + 1] * stride + e] * t[TB_UMUL] + t[TB_UADD];
-    const double g = (double)planes[(int64_t)itbl[k * ITS + 2] * stride + e];
-    const double Dr = t[TB_M2] - s, Di = t[TB_NGE] * g;
+    const double s = at(k, IT_S), g = at(k, IT_G);
+    const double h = gen ? at(k, IT_H) : 0.0;
+    // D = (M^2 - s) - i Gamma eta (g + i h)
+    const double Dr = t[TB_M2] - s - t[TB_NGE] * h, Di = t[TB_NGE] * g;
     const double inv = 1.0 / (Dr * Dr + Di * Di);
-    const double uwr = u * Dr * inv, uwi = -u * Di * inv;
-    zr += t[TB_CBR] * uwr - t[TB_CBI] * uwi;
-    zi += t[TB_CBR] * uwi + t[TB_CBI] * uwr;
+    const double wr = Dr * inv, wi = -Di * inv;
+    for (int mu = 0; mu < nmu; ++mu) {
+      const double ur = mu == 0 ? at(k, IT_U) * t[TB_UMUL] + t[TB_UADD] : at(k, IT_U1R);
+      const double ui = gen ? (mu == 0 ? at(k, IT_UI) : at(k, IT_U1I)) : 0.0;
+      const double uwr = ur * wr - ui * wi, uwi = ur * wi + ui * wr;
+      zr[mu] += t[TB_CBR] * uwr - t[TB_CBI] * uwi;
+      zi[mu] += t[TB_CBR] * uwi + t[TB_CBI] * uwr;
+    }
   }
-  out[i] = zr * zr + zi * zi;
+  double w = 0.0;
+  for (int mu = 0; mu < nmu; ++mu) w += zr[mu] * zr[mu] + zi[mu] * zi[mu];
+  out[i] = w;
 }
 
 // ------------------------------------------------------------------------
 // Launchers and the table of built launch shapes.
 // ------------------------------------------------------------------------
-hipError_t launch_precompute(const double* s12, const double* s13, int64_t n, int64_t offset,
-                             void* planes, int64_t stride, int is_f32, const ModelDev& md,
-                             const FieldSpec& fs, hipStream_t st) {
+hipError_t launch_precompute(const double* s12, const double* s13, const double* cosb,
+                             const double* gam, int64_t n, int64_t offset, void* planes,
+                             int64_t stride, int is_f32, const ModelDev& md, const FieldSpec& fs,
+                             hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((n + 255) / 256);
   if (is_f32)
-    hipLaunchKernelGGL(precompute_kernel<float>, dim3(grid), dim3(256), 0, st, s12, s13, n,
-                       offset, (float*)planes, stride, md, fs);
+    hipLaunchKernelGGL(precompute_kernel<float>, dim3(grid), dim3(256), 0, st, s12, s13, cosb, gam,
+                       n, offset, (float*)planes, stride, md, fs);
   else
-    hipLaunchKernelGGL(precompute_kernel<double>, dim3(grid), dim3(256), 0, st, s12, s13, n,
-                       offset, (double*)planes, stride, md, fs);
+    hipLaunchKernelGGL(precompute_kernel<double>, dim3(grid), dim3(256), 0, st, s12, s13, cosb, gam,
+                       n, offset, (double*)planes, stride, md, fs);
   return hipGetLastError();
 }
 
 hipError_t launch_intensity(bool f32, const void* planes, int64_t stride, int64_t base, int64_t n,
-                            const double* tbl, const int* itbl, int K, double* out,
-                            hipStream_t st) {
+                            const double* tbl, const int* itbl, int K, int gen, int nmu,
+                            double* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((n + 255) / 256);
   if (f32)
     hipLaunchKernelGGL(intensity_kernel<float>, dim3(grid), dim3(256), 0, st, (const float*)planes,
-                       stride, base, n, tbl, itbl, K, out);
+                       stride, base, n, tbl, itbl, K, gen, nmu, out);
   else
     hipLaunchKernelGGL(intensity_kernel<double>, dim3(grid), dim3(256), 0, st,
-                       (const double*)planes, stride, base, n, tbl, itbl, K, out);
+                       (const double*)planes, stride, base, n, tbl, itbl, K, gen, nmu, out);
   return hipGetLastError();
 }
 
@@ -1296,9 +1759,37 @@ static EvalFn wg_fn(int is_f32, int mode, int G, int R) {
   return nullptr;
 }
 
+// General physics path shapes (waves per block G, resonances per wave R).
+#define PWA_GEN_SHAPES(X) X(1, 2) X(2, 2) X(4, 2) X(8, 2)
+
+bool gen_shape_built(int G, int R) {
+#define PWA_IS(GG, RR) if (G == GG && R == RR) return true;
+  PWA_GEN_SHAPES(PWA_IS)
+#undef PWA_IS
+  return false;
+}
+
+static EvalFn gen_fn(int is_f32, int mode, int G, int R) {
+#define PWA_PICK(GG, RR)                                                              \
+  if (G == GG && R == RR) {                                                           \
+    if (mode == MODE_NLL)                                                             \
+      return is_f32 ? wgx_kernel<float, MODE_NLL, GG, RR> : wgx_kernel<double, MODE_NLL, GG, RR>;   \
+    if (mode == MODE_GRAD)                                                            \
+      return is_f32 ? wgx_kernel<float, MODE_GRAD, GG, RR> : wgx_kernel<double, MODE_GRAD, GG, RR>; \
+    if (mode == MODE_HVPB)                                                            \
+      return is_f32 ? wgx_kernel<float, MODE_HVPB, GG, RR> : wgx_kernel<double, MODE_HVPB, GG, RR>; \
+    return is_f32 ? wgx_kernel<float, MODE_HVP, GG, RR> : wgx_kernel<double, MODE_HVP, GG, RR>;     \
+  }
+  PWA_GEN_SHAPES(PWA_PICK)
+#undef PWA_PICK
+  return nullptr;
+}
+
 // layout 1: team (T lanes of a wave per event, 256-thread blocks);
-// layout 2: wave group (G waves per 64 events, 64 G-thread blocks).
+// layout 2: wave group (G waves per 64 events, 64 G-thread blocks);
+// layout 3: wave group of the general physics path.
 static EvalFn pick_fn(int is_f32, int mode, int layout, int T, int R) {
+  if (layout == 3) return gen_fn(is_f32, mode, T, R);
   if (layout == 2) return wg_fn(is_f32, mode, T, R);
   if (mode == MODE_NLL && T == 1 && nll_shape_built(R)) return nll_fn(is_f32, R);
   return eval_fn(is_f32, mode, T, R);
@@ -1308,16 +1799,18 @@ hipError_t launch_eval(int is_f32, int mode, int layout, int T, int R, const Eva
                        int nblocks, hipStream_t st) {
   EvalFn fn = pick_fn(is_f32, mode, layout, T, R);
   if (!fn) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fn, dim3(nblocks), dim3(layout == 2 ? 64 * T : BLOCK), 0, st, a);
+  const size_t lds = layout == 2 ? stage_lds_bytes(a.n_fields, is_f32 ? 4 : 8) : 0;
+  hipLaunchKernelGGL(fn, dim3(nblocks), dim3(layout >= 2 ? 64 * T : BLOCK), lds, st, a);
   return hipGetLastError();
 }
 
-int eval_occupancy(int is_f32, int mode, int layout, int T, int R) {
+int eval_occupancy(int is_f32, int mode, int layout, int T, int R, int n_fields) {
   EvalFn fn = pick_fn(is_f32, mode, layout, T, R);
   if (!fn) return 0;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, layout == 2 ? 64 * T : BLOCK,
-                                                   0) != hipSuccess)
+  const size_t lds = layout == 2 ? stage_lds_bytes(n_fields, is_f32 ? 4 : 8) : 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, layout >= 2 ? 64 * T : BLOCK,
+                                                   lds) != hipSuccess)
     return 0;
   return nb;
 }

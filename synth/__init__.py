@@ -9,10 +9,11 @@ intensity (accept-reject), the caller passes it in.
 """
 
 from .workloads import (  # noqa: F401
-    PARENT_MASS, DAUGHTER_MASSES, R_BARRIER, CHANNEL_PAIRS,
+    PARENT_MASS, DAUGHTER_MASSES, R_BARRIER, CHANNEL_PAIRS, FLATTE_MASSES, FLATTE_RATIO, FLATTE_F0,
     Workload, workload, rng_for, draw_theta, resonance_layout,
 )
 from .events import (  # noqa: F401
     pair_range, s13_range, bounding_box, uniform_phase_space,
     mirror_symmetric, midpoint_line_s12, midpoint_grid, resonant_like, accept_reject,
+    uniform_orientation,
 )

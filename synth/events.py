@@ -170,3 +170,11 @@ def accept_reject(n, intensity, rng, parent=PARENT_MASS, masses=DAUGHTER_MASSES,
         if not bad:
             return np.concatenate(out12)[:n].copy(), np.concatenate(out13)[:n].copy()
         wmax *= 2.0
+
+
+def uniform_orientation(n: int, rng: np.random.Generator):
+    """Orientation of n decays, uniform over rotations: (cos beta, gamma)
+    with cos beta ~ U[-1, 1] and gamma ~ U[0, 2 pi) (the third Euler angle,
+    a rotation about the polarisation axis, does not enter a helicity-summed
+    intensity)."""
+    return rng.uniform(-1.0, 1.0, n), rng.uniform(0.0, 2.0 * np.pi, n)

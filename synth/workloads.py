@@ -21,6 +21,15 @@ PARENT_MASS = 1.865
 DAUGHTER_MASSES = (0.494, 0.140, 0.140)
 R_BARRIER = 3.0  # Blatt-Weisskopf radius, GeV^-1
 
+# Coupled second channel of a Flatte (scalar) resonance: a K Kbar pair and
+# the coupling ratio g_2 / g_1, values of the size quoted for f0(980) fits;
+# with f0-like M = 0.965 GeV and g_1 = 0.165 GeV^2 in the (23) channel (the
+# pi pi pair of these daughters) the K Kbar threshold (0.975 GeV^2) lies
+# inside the Dalitz region.
+FLATTE_MASSES = (0.493677, 0.493677)
+FLATTE_RATIO = 4.21
+FLATTE_F0 = (0.965, 0.165)   # (M, g_1)
+
 # Channel c -> (a, b, bachelor) as 0-based daughter indices:
 #   0 = (12) with bachelor 3, 1 = (13) with bachelor 2, 2 = (23) with bachelor 1.
 CHANNEL_PAIRS = ((0, 1, 2), (0, 2, 1), (1, 2, 0))

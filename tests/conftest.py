@@ -16,7 +16,7 @@ def pytest_configure(config):
 class _Model:
     """Minimal model description accepted by the oracle (duck-typed)."""
 
-    def __init__(self, channel, spin, width_mode=0):
+    def __init__(self, channel, spin, width_mode=0, lineshape=None, flatte_ratio=None):
         import synth
         self.channel = list(channel)
         self.spin = list(spin)
@@ -25,6 +25,9 @@ class _Model:
         self.masses = synth.DAUGHTER_MASSES
         self.r = synth.R_BARRIER
         self.n_res = len(self.channel)
+        self.lineshape = None if lineshape is None else list(lineshape)
+        self.flatte_masses = synth.FLATTE_MASSES
+        self.flatte_ratio = synth.FLATTE_RATIO if flatte_ratio is None else flatte_ratio
 
 
 @pytest.fixture

@@ -93,7 +93,7 @@ def bw_factor_sq(J, z):
     return 1 / (z ** J * (x * x) * sph_hankel_abs2(J, x))
 
 
-def amp(kin, ch, J, M, G, m, r, width_mode=0):
+def amp(kin, ch, J, M, G, m, r, width_mode=0, ang=None):
     s, q, cos = kin
     a, b, _ = PAIRS[ch]
     ma, mb = mp.mpf(m[a]), mp.mpf(m[b])
@@ -104,7 +104,55 @@ def amp(kin, ch, J, M, G, m, r, width_mode=0):
         gs = G * (q / q0) ** (2 * J + 1) * (M / mp.sqrt(s)) * ratio ** 2
     else:
         gs = G
-    return mp.legendre(J, cos) * ratio / (M ** 2 - s - 1j * M * gs)
+    a_ = mp.legendre(J, cos) if ang is None else ang
+    return a_ * ratio / (M ** 2 - s - 1j * M * gs)
+
+
+def _unit3(v):
+    n = mp.sqrt(v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+    return [x / n for x in v]
+
+
+def spin1_omega(s12, s13, cosb, gam, channel, spin, th, M, m, r):
+    """sum over mu = +1, -1 of |sum_k c_k Y_J^mu a_k|^2 for a vector parent:
+    four-vectors from the (12) frame boosted to the parent rest frame, turned
+    to the reference plane (p_1 along x, p_2 in the upper x-y half plane),
+    rotated by R_y(beta) R_z(gamma); Y from the bachelor direction and the
+    direction of a boosted into the pair's rest frame."""
+    vecs = four_vectors(s12, s13, M, m)
+    P = _add(_add(vecs[0], vecs[1]), vecs[2])
+    vp = [_boost_to_rest(v, P) for v in vecs]
+    e1 = _unit3(vp[0][1:])
+    d = sum(vp[1][1 + i] * e1[i] for i in range(3))
+    e2 = _unit3([vp[1][1 + i] - d * e1[i] for i in range(3)])
+    e3 = [e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]]
+    cb = mp.mpf(cosb)
+    sb = mp.sqrt(1 - cb * cb)
+    cg, sg = mp.cos(mp.mpf(gam)), mp.sin(mp.mpf(gam))
+    lab = []
+    for v in vp:
+        x, y, z = (sum(v[1 + i] * e[i] for i in range(3)) for e in (e1, e2, e3))
+        xr, yr = x * cg - y * sg, x * sg + y * cg          # R_z(gamma)
+        lab.append([v[0], xr * cb + z * sb, yr, -xr * sb + z * cb])   # R_y(beta)
+    zmu = [mp.mpc(0), mp.mpc(0)]
+    for k, (ch, J) in enumerate(zip(channel, spin)):
+        a, b, c = PAIRS[ch]
+        pc = _unit3(lab[c][1:])
+        qa = _unit3(_boost_to_rest(lab[a], _add(lab[a], lab[b]))[1:])
+        if J == 0:
+            vv = pc
+        elif J == 1:
+            vv = [pc[1] * qa[2] - pc[2] * qa[1], pc[2] * qa[0] - pc[0] * qa[2], pc[0] * qa[1] - pc[1] * qa[0]]
+        else:
+            qp = sum(qa[i] * pc[i] for i in range(3))
+            vv = [qa[i] * qp - pc[i] / 3 for i in range(3)]
+        ys = (-(vv[0] + 1j * vv[1]) / mp.sqrt(2), (vv[0] - 1j * vv[1]) / mp.sqrt(2))
+        kin = channel_kin(vecs, ch)
+        cpl = mp.mpf(th[4 * k]) + 1j * mp.mpf(th[4 * k + 1])
+        for mu in range(2):
+            zmu[mu] += cpl * amp(kin, ch, J, mp.mpf(th[4 * k + 2]), mp.mpf(th[4 * k + 3]), m, r,
+                                 0, ys[mu])
+    return abs(zmu[0]) ** 2 + abs(zmu[1]) ** 2
 
 
 class TinyNLL:

@@ -143,6 +143,9 @@ def test_unbound_and_bad_bind_arguments(lib):
         opts.xtol = 1e-8
         assert lib.pwa_fit(h, fake, ctypes.byref(opts), None, st) == L.PWA_E_STATE
         assert lib.pwa_fit(h, fake, None, None, st) == L.PWA_E_INVALID
+        assert lib.pwa_fit_bfgs(h, fake, ctypes.byref(opts), None, st) == L.PWA_E_STATE
+        assert lib.pwa_fit_bfgs(h, fake, None, None, st) == L.PWA_E_INVALID
+        assert lib.pwa_fit_bfgs(None, fake, ctypes.byref(opts), None, st) == L.PWA_E_INVALID
         need = lib.pwa_workspace_bytes(h, 10, 10)
         # n_mc < 1, negative n_data, null MC pointers
         assert lib.pwa_bind(h, fake, fake, 10, fake, fake, 0, fake, need, st) == L.PWA_E_INVALID
@@ -199,13 +202,13 @@ def test_mlp_host_validation(lib):
 
 
 def test_event_count_limit(lib):
-    """Planes are addressed with 32-bit byte offsets: at most 2^29 - 64 events
-    per context (FP64); beyond that the workspace query returns 0 and bind
-    rejects the sizes before any device call."""
+    """Planes are addressed with 32-bit byte offsets: at most 2^29 - 256
+    events per context (FP64 stream); beyond that the workspace query returns
+    0 and bind rejects the sizes before any device call."""
     code, h = _create(lib, _model())
     assert code == L.PWA_OK
     try:
-        lim = (1 << 29) - 64
+        lim = (1 << 29) - 256
         assert lib.pwa_workspace_bytes(h, lim - 10, 10) > 0
         assert lib.pwa_workspace_bytes(h, lim - 9, 10) == 0
         fake = ctypes.c_void_p(0x1000)
@@ -294,3 +297,58 @@ def test_fraction_matrix_limits(lib):
             assert (lib.pwa_fraction_matrix_workspace_bytes(h) > 0) == ok
         finally:
             lib.pwa_destroy(h)
+
+
+def test_general_physics_model_validation(lib):
+    """Flatte only for scalars, its second channel and ratio valid, a parent
+    spin of 0 or 1, at most 16 resonances on the general path; each bind
+    entry point serves its own parent spin and layout 3 its own models.
+    All rejected on the host, before any device call."""
+    fake = ctypes.c_void_p(0x1000)
+    m = _model(2, spin=[0, 1])
+    m.lineshape[1] = L.PWA_LINESHAPE_FLATTE          # J = 1: not a scalar
+    m.flatte_masses[0] = m.flatte_masses[1] = 0.4937
+    m.flatte_ratio = 4.0
+    assert _create(lib, m)[0] == L.PWA_E_INVALID
+    m = _model(2, spin=[0, 1])
+    m.lineshape[0] = L.PWA_LINESHAPE_FLATTE
+    m.flatte_ratio = 4.0                              # second-channel masses unset
+    assert _create(lib, m)[0] == L.PWA_E_INVALID
+    m.flatte_masses[0] = m.flatte_masses[1] = 0.4937
+    m.flatte_ratio = -1.0
+    assert _create(lib, m)[0] == L.PWA_E_INVALID
+    m.flatte_ratio = 4.0
+    m.lineshape[1] = 7
+    assert _create(lib, m)[0] == L.PWA_E_INVALID
+    m.lineshape[1] = 0
+    code, h = _create(lib, m)
+    assert code == L.PWA_OK
+    try:
+        assert lib.pwa_set_launch_shape(h, 2, 1, 2) == L.PWA_E_INVALID
+        assert lib.pwa_set_launch_shape(h, 3, 1, 2) == L.PWA_OK
+        assert lib.pwa_set_launch_shape(h, 3, 3, 2) == L.PWA_E_INVALID   # not built
+        assert lib.pwa_bind_oriented(h, fake, fake, fake, fake, 10, fake, fake, fake, fake, 10,
+                                     fake, 1 << 30, None) == L.PWA_E_INVALID
+    finally:
+        lib.pwa_destroy(h)
+    m = _model(3)
+    m.parent_spin = 2
+    assert _create(lib, m)[0] == L.PWA_E_INVALID
+    m.parent_spin = 1
+    code, h = _create(lib, m)
+    assert code == L.PWA_OK
+    try:
+        assert lib.pwa_bind(h, fake, fake, 10, fake, fake, 10, fake, 1 << 30, None) == L.PWA_E_INVALID
+        # orientation arrays are required
+        assert lib.pwa_bind_oriented(h, fake, fake, None, fake, 10, fake, fake, fake, fake, 10,
+                                     fake, 1 << 30, None) == L.PWA_E_INVALID
+        assert lib.pwa_fraction_matrix_workspace_bytes(h) == 0
+    finally:
+        lib.pwa_destroy(h)
+    m = _model(17)
+    m.parent_spin = 1
+    assert _create(lib, m)[0] == L.PWA_E_INVALID
+    m = _model(17)
+    code, h = _create(lib, m)
+    assert code == L.PWA_OK
+    lib.pwa_destroy(h)
