@@ -325,7 +325,7 @@ def batched_bench(reps=5):
     out = {"workload": f"K={W.n_res} frozen masses/widths, {W.n_data} data + {W.n_mc} MC, "
                        f"B={B} coupling vectors", "formats": {}}
     ref = None
-    for fmt in ("f64", "f32", "f16x3", "f16", "bf16"):
+    for fmt in ("f64", "f32", "f16s", "f16", "bf16"):
         lik.freeze(W.theta_true, fmt, B)
         nll = lik.nll_batched(C)
         torch.cuda.synchronize()

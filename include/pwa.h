@@ -434,19 +434,30 @@ int pwa_kernel_time(pwa_ctx* ctx, double* total_ms, int64_t* n_launches);
 /* Operand formats.  A rounding of a coupling shifts every event's log the
  * same way (the NLL error grows like N_D times the gradient in c), while a
  * rounding of an amplitude is independent from event to event (its error
- * grows like sqrt(N_D)); the accurate formats therefore represent the
- * couplings as a sum of parts.  BF16 and FP16 round both operands once and
- * are the fast, low-precision formats. */
+ * grows like sqrt(N_D)).  BF16 and FP16 round both operands once and are the
+ * fast, low-precision formats.
+ *
+ * The sliced FP16 format runs on the FP16 matrix cores with fixed-point
+ * operands.  Each event's amplitude row is scaled by a power of two, 2^(9-E)
+ * with |largest component| < 2^E, and cut into four integer slices
+ * x = 2^(E-9) (q0 + 2^-9 q1 + 2^-18 q2 + 2^-27 q3) + r with |q0| <= 512,
+ * |q1..q3| <= 256 and |r| <= 2^(E-37); each start's couplings are cut the
+ * same way with the exponent of its largest real or imaginary component.
+ * Z = sum over slice pairs (i, j) with i + j <= 3 of 2^(-9 (i + j)) q^A_i . q^C_j
+ * (ten products) times the two powers of two.  Every slice product is an
+ * integer, so the leading dot product (at most 48 terms below 2^18) is formed
+ * exactly in FP32 and the next two levels are too; the levels are combined in
+ * FP64 and the logs are FP64.  Representation error: 2^-28 of the row's
+ * largest amplitude (random over events) and 2^-37 of the start's largest
+ * coupling (the same for every event). */
 typedef enum pwa_operand {
   PWA_OP_F64 = 0,   /* FP64 operands, FP64 matrix-core accumulation          */
   PWA_OP_F32 = 1,   /* FP32 amplitudes; couplings as FP32 hi + lo (two
                        products); FP32 accumulation                          */
   PWA_OP_BF16 = 2,  /* BF16 operands, FP32 accumulation                      */
   PWA_OP_F16 = 3,   /* FP16 operands, FP32 accumulation                      */
-  PWA_OP_F16X3 = 4  /* FP16 amplitudes as hi + lo; couplings, scaled per
-                       start by a power of two, as three FP16 parts; four
-                       products (hi*c0 + hi*c1 + hi*c2 + lo*c0), FP32
-                       accumulation                                          */
+  PWA_OP_F16S = 4   /* sliced FP16 (above): four 9-bit fixed-point slices of
+                       each operand, ten exact integer products              */
 } pwa_operand;
 
 /* Device workspace (bytes) of the batched path for n_data data events,

@@ -759,28 +759,86 @@ def round_to(x, fmt):
     raise ValueError(fmt)
 
 
+# Sliced FP16 operand format of the batched path: fixed-point slices.
+SLICE_BITS = 9
+SLICE_COUNT = 4
+SLICE_LEVELS = 3   # slice pairs (i, j) with i + j <= 3 are multiplied
+
+
+def fixed_slices(x, axis, count=SLICE_COUNT, bits=SLICE_BITS):
+    """Cut every vector of x along `axis` into `count` integer slices: with E
+    the exponent of the vector's largest real or imaginary magnitude
+    (|max| < 2^E; E = 0 for a zero vector),
+        x 2^(bits - E) = q_0 + 2^-bits q_1 + ... + 2^-(bits (count-1)) q_(count-1) + r,
+    each q_s the nearest integer (ties to even) of the running remainder,
+    which is then scaled by 2^bits.  Real and imaginary parts are cut
+    separately with their common E.  Returns (list of q_s, E with the
+    reduced axis kept)."""
+    x = np.asarray(x)
+    cplx = np.iscomplexobj(x)
+    mag = np.maximum(np.abs(x.real), np.abs(x.imag)) if cplx else np.abs(x)
+    m = np.max(mag, axis=axis, keepdims=True)
+    E = np.where(m > 0, np.frexp(m)[1], 0)
+
+    def cut(v):
+        v = v * np.ldexp(1.0, bits - E)
+        out = []
+        for _ in range(count):
+            q = np.rint(v)
+            out.append(q)
+            v = (v - q) * 2.0 ** bits
+        return out
+
+    if cplx:
+        return [r + 1j * i for r, i in zip(cut(x.real), cut(x.imag))], E
+    return cut(x), E
+
+
+def sliced_product(A, C):
+    """A @ C as the sliced FP16 format defines it: A cut per row, C per
+    column, and only the slice pairs i + j <= SLICE_LEVELS multiplied:
+        Z = 2^(E_row + G_col - 2 bits) sum_{i+j<=L} 2^(-bits (i+j)) q^A_i @ q^C_j.
+    Every slice product is an integer dot product, exact in FP64, and the
+    weighted sum spans fewer than 53 bits, so Z carries no rounding beyond
+    the format's own."""
+    qa, Ea = fixed_slices(A, axis=1)
+    qc, Gc = fixed_slices(C, axis=0)
+    Z = np.zeros((A.shape[0], C.shape[1]), dtype=complex)
+    for i in range(SLICE_COUNT):
+        for j in range(SLICE_COUNT):
+            if i + j <= SLICE_LEVELS:
+                Z += np.ldexp(1.0, -SLICE_BITS * (i + j)) * (qa[i] @ qc[j])
+    return Z * np.ldexp(1.0, Ea + Gc - 2 * SLICE_BITS)
+
+
 def nll_batched(data, mc, model, theta, C, fmt="f64", chunk=50_000, parts=False):
     """NLL_b = -sum_data ln |(A_D c_b)_i|^2 + N_D ln( c_b^H Gm c_b / N_MC )
     for every column c_b of the complex K x B matrix C (M, Gamma frozen at
-    theta).  With fmt != 'f64' the operands A and C are first rounded to
-    that format (the contraction itself stays FP64), which isolates the
-    error due to operand rounding.  With parts=True returns (F_b, G_b)."""
+    theta).  With fmt in ('f32', 'bf16', 'f16') the operands A and C are
+    first rounded to that format (the contraction itself stays FP64), which
+    isolates the error due to operand rounding; with fmt = 'f16s' the
+    products are the sliced format's (sliced_product).  With parts=True
+    returns (F_b, G_b)."""
     C = np.asarray(C, dtype=complex)
-    Cr = round_to(C.real, fmt) + 1j * round_to(C.imag, fmt)
     B = C.shape[1]
+    if fmt == "f16s":
+        def zmat(ev):
+            return sliced_product(np.stack(amplitudes(ev, model, theta), axis=1), C)
+    else:
+        Cr = round_to(C.real, fmt) + 1j * round_to(C.imag, fmt)
 
-    def amat(ev):
-        A = np.stack(amplitudes(ev, model, theta), axis=1)
-        return round_to(A.real, fmt) + 1j * round_to(A.imag, fmt)
+        def zmat(ev):
+            A = np.stack(amplitudes(ev, model, theta), axis=1)
+            return (round_to(A.real, fmt) + 1j * round_to(A.imag, fmt)) @ Cr
 
     Fp, Gp = [], []
     for ev in _chunks(data, chunk):
         if len(ev[0]):
-            Z = amat(ev) @ Cr
+            Z = zmat(ev)
             Fp.append(np.log(Z.real ** 2 + Z.imag ** 2))
     for ev in _chunks(mc, chunk):
         if len(ev[0]):
-            Z = amat(ev) @ Cr
+            Z = zmat(ev)
             Gp.append(Z.real ** 2 + Z.imag ** 2)
     F = np.array([math.fsum(np.concatenate([p[:, b] for p in Fp])) for b in range(B)])
     G = np.array([math.fsum(np.concatenate([p[:, b] for p in Gp])) for b in range(B)])

@@ -26,7 +26,7 @@ PWA_STREAM_F64 = 1
 PWA_STREAM_F32 = 2
 PWA_LINESHAPE_BREIT_WIGNER = 0
 PWA_LINESHAPE_FLATTE = 1
-OPERANDS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f16x3": 4}
+OPERANDS = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3, "f16s": 4}
 
 c_double, c_int32, c_int64, c_size_t, c_void_p = (
     ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p)

@@ -4,6 +4,7 @@
 
 Compiles csrc/pwa_kernels.hip (likelihood kernels and launchers),
 csrc/pwa_batched.hip (fixed-lineshape batched path on the matrix cores),
+csrc/pwa_sliced.hip (its sliced FP16 format, MFMA results in VGPRs),
 csrc/pwa_mlp.hip (histograms and the start-proposal MLP),
 csrc/pwa_analysis.hip (Hessian columns and fit fractions at a minimum) and
 csrc/pwa_api.cpp (C ABI, workspace layout, Newton-CG driver) with hipcc and
@@ -46,6 +47,7 @@ def build(verbose=False, jobs=2):
     os.makedirs(bdir, exist_ok=True)
     k_obj = os.path.join(bdir, "pwa_kernels.o")
     b_obj = os.path.join(bdir, "pwa_batched.o")
+    s_obj = os.path.join(bdir, "pwa_sliced.o")
     a_obj = os.path.join(bdir, "pwa_api.o")
     m_obj = os.path.join(bdir, "pwa_mlp.o")
     x_obj = os.path.join(bdir, "pwa_analysis.o")
@@ -54,6 +56,8 @@ def build(verbose=False, jobs=2):
         [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_kernels.hip"), "-o", k_obj],
         [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_analysis.hip"), "-o", x_obj],
         [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "pwa_batched.hip"), "-o", b_obj],
+        [HIPCC] + COMMON + DEVICE + ["-mllvm", "-amdgpu-mfma-vgpr-form",
+                                     "-c", os.path.join(CSRC, "pwa_sliced.hip"), "-o", s_obj],
         [HIPCC] + COMMON + DEVICE + ["-x", "hip", "-c", os.path.join(CSRC, "pwa_api.cpp"), "-o", a_obj],
     ]
     procs = [subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
@@ -66,7 +70,8 @@ def build(verbose=False, jobs=2):
             sys.stderr.write(out + err)
             raise RuntimeError("hipcc failed for " + c[-3])
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, b_obj, a_obj, m_obj, x_obj],
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, k_obj, b_obj, s_obj, a_obj, m_obj,
+          x_obj],
          verbose)
     os.replace(tmp, LIB)
     if verbose:

@@ -50,11 +50,9 @@ struct pwa_ctx {
   // batched (frozen-lineshape) path
   bool frozen = false;
   int bfmt = 0, bKP = 0, bmax = 0, brows = 0, bgram_blocks = 0;
-  void* bA_hi = nullptr;
-  void* bA_lo = nullptr;
-  void* bC_hi = nullptr;
-  void* bC_lo = nullptr;
-  void* bC_lo2 = nullptr;
+  void* bA[kSlices] = {};             // amplitude operand planes
+  void* bC[kSlices] = {};             // coupling operand planes
+  unsigned long long* besum = nullptr;   // sliced format: sum of the row exponents
   double* bpart = nullptr;
   double* bpart2 = nullptr;
   double* bgram_part = nullptr;
@@ -1236,7 +1234,8 @@ constexpr int kGramBlocks = 512;
 constexpr int kGP = 48;
 
 struct BLayout {
-  size_t A_hi, A_lo, C_hi, C_lo, C_lo2, part, part2, gpart, gram, total;
+  size_t A, C, esum, part, part2, gpart, gram, total;
+  size_t a_plane, c_plane;   // bytes per operand plane
   int KP;
 };
 
@@ -1250,13 +1249,12 @@ BLayout blayout(const pwa_ctx* c, int64_t n_data, int fmt, int max_batch) {
   };
   L.KP = batched_kp(fmt, c->K);
   const size_t eb = batched_elem_bytes(fmt);
-  const bool split = fmt == PWA_OP_F16X3;
-  L.A_hi = take(std::max<int64_t>(n_data, 1) * L.KP * eb);
-  L.A_lo = take(split ? std::max<int64_t>(n_data, 1) * L.KP * eb : 0);
-  const int ncp = fmt == PWA_OP_F32 ? 2 : (split ? 3 : 1);   // coupling parts
-  L.C_hi = take((size_t)L.KP * 2 * max_batch * eb);
-  L.C_lo = take(ncp > 1 ? (size_t)L.KP * 2 * max_batch * eb : 0);
-  L.C_lo2 = take(ncp > 2 ? (size_t)L.KP * 2 * max_batch * eb : 0);
+  // planes of one operand are contiguous (the sliced kernels index them so)
+  L.a_plane = (size_t)n_data * L.KP * eb;
+  L.c_plane = (size_t)L.KP * 2 * max_batch * eb;
+  L.A = take(std::max<size_t>(L.a_plane * batched_a_planes(fmt), 1));
+  L.C = take(L.c_plane * batched_c_planes(fmt));
+  L.esum = take(sizeof(unsigned long long));
   L.part = take(sizeof(double) * 2 * (size_t)kBatchRowBlocks * max_batch);
   L.part2 = take(sizeof(double) * 2 * (size_t)kBatchChunks * max_batch);
   L.gpart = take(sizeof(double) * 2 * (size_t)kGramBlocks * kGP * kGP);
@@ -1268,7 +1266,7 @@ BLayout blayout(const pwa_ctx* c, int64_t n_data, int fmt, int max_batch) {
 
 size_t pwa_batched_workspace_bytes(const pwa_ctx* c, int64_t n_data, int32_t fmt,
                                    int32_t max_batch) {
-  if (!c || n_data < 0 || fmt < PWA_OP_F64 || fmt > PWA_OP_F16X3) return 0;
+  if (!c || n_data < 0 || fmt < PWA_OP_F64 || fmt > PWA_OP_F16S) return 0;
   if (max_batch < 1 || max_batch > 65536 || 2 * c->K > kGP) return 0;
   return blayout(c, n_data, fmt, max_batch).total;
 }
@@ -1276,7 +1274,7 @@ size_t pwa_batched_workspace_bytes(const pwa_ctx* c, int64_t n_data, int32_t fmt
 int pwa_freeze(pwa_ctx* c, const double* d_theta, int32_t fmt, int32_t max_batch, void* d_bws,
                size_t bws_bytes, hipStream_t st) {
   if (!c || !d_theta) return PWA_E_INVALID;
-  if (fmt < PWA_OP_F64 || fmt > PWA_OP_F16X3 || max_batch < 1 || max_batch > 65536) return PWA_E_INVALID;
+  if (fmt < PWA_OP_F64 || fmt > PWA_OP_F16S || max_batch < 1 || max_batch > 65536) return PWA_E_INVALID;
   if (2 * c->K > kGP) return PWA_E_INVALID;
   // one amplitude row per event: a spin-1 parent's two helicity amplitudes
   // are not laid out on this path
@@ -1291,22 +1289,24 @@ int pwa_freeze(pwa_ctx* c, const double* d_theta, int32_t fmt, int32_t max_batch
   c->bfmt = fmt;
   c->bKP = L.KP;
   c->bmax = max_batch;
-  c->bA_hi = w + L.A_hi;
-  c->bA_lo = fmt == PWA_OP_F16X3 ? (void*)(w + L.A_lo) : nullptr;
-  c->bC_hi = w + L.C_hi;
-  c->bC_lo = (fmt == PWA_OP_F16X3 || fmt == PWA_OP_F32) ? (void*)(w + L.C_lo) : nullptr;
-  c->bC_lo2 = fmt == PWA_OP_F16X3 ? (void*)(w + L.C_lo2) : nullptr;
+  for (int s = 0; s < kSlices; ++s) {
+    c->bA[s] = s < batched_a_planes(fmt) ? (void*)(w + L.A + s * L.a_plane) : nullptr;
+    c->bC[s] = s < batched_c_planes(fmt) ? (void*)(w + L.C + s * L.c_plane) : nullptr;
+  }
+  c->besum = (unsigned long long*)(w + L.esum);
   c->bpart = (double*)(w + L.part);
   c->bpart2 = (double*)(w + L.part2);
   c->bgram_part = (double*)(w + L.gpart);
   c->bgram = (double*)(w + L.gram);
-  c->brows = (int)std::max<int64_t>(1, std::min<int64_t>(kBatchRowBlocks, (c->n_data + 63) / 64));
+  // a multiple of 8: the sliced kernel places the chunk blocks of one row
+  // block on one XCD
+  c->brows = (int)std::min<int64_t>(kBatchRowBlocks, std::max<int64_t>(8, ((c->n_data + 63) / 64 + 7) / 8 * 8));
   c->bgram_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kGramBlocks, (c->n_mc + 255) / 256));
   // resonance table at theta (v = 0): frozen M, Gamma
   if (launch_table(d_theta, nullptr, c->md, c->K, c->tbl64, c->tbl32, c->itbl, c->status, st) != hipSuccess)
     return PWA_E_HIP;
   if (launch_freeze(fmt, c->planes64, c->stride, c->n_data, c->tbl64, c->itbl, c->K, L.KP,
-                    c->md.gen, c->bA_hi, c->bA_lo, st) != hipSuccess)
+                    c->md.gen, c->bA, c->besum, st) != hipSuccess)
     return PWA_E_HIP;
   if (launch_gram(c->planes64, c->stride, c->mc_off, c->n_mc, c->tbl64, c->itbl, c->K, c->md.gen,
                   c->bgram_blocks, c->bgram_part, c->bgram, st) != hipSuccess)
@@ -1320,11 +1320,11 @@ int pwa_nll_batched(pwa_ctx* c, const double* d_C, int32_t B, double* d_nll, hip
   if (!c->frozen) return PWA_E_STATE;
   if (B < 1 || B > c->bmax) return PWA_E_INVALID;
   BatchArgs a;
-  a.A_hi = c->bA_hi;
-  a.A_lo = c->bA_lo;
-  a.C_hi = c->bC_hi;
-  a.C_lo = c->bC_lo;
-  a.C_lo2 = c->bC_lo2;
+  for (int s = 0; s < kSlices; ++s) {
+    a.A[s] = c->bA[s];
+    a.C[s] = c->bC[s];
+  }
+  a.esum = c->besum;
   a.KP = c->bKP;
   a.B = B;
   a.n = c->n_data;

@@ -10,7 +10,8 @@
 // The complex product is the real GEMM
 //   [Zr | Zi] = [Ar | Ai] . [[Cr, Ci], [-Ci, Cr]]
 // run on MFMA in the chosen operand format with FP32 accumulation (FP64 for
-// the FP64 format).  The log epilogue is fused: Z never reaches memory.
+// the FP64 format; exact integer sums for the sliced FP16 format).  The log
+// epilogue is fused: Z never reaches memory.
 // Per lane, the 4 rows of an MFMA result tile are combined as the product of
 // their mantissas (one logarithm per 4 events) with the exponents summed as
 // integers; per-start sums are FP64, reduced across blocks in double-double.
@@ -19,144 +20,51 @@
 #include <math.h>
 
 #include "pwa_batched.h"
+#include "pwa_batched_dev.h"
 
 namespace pwa {
-
-typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
-typedef short s4_t __attribute__((ext_vector_type(4)));
-typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void dd_add_b(double& hi, double& lo, double bhi, double blo) {
-  const double s = hi + bhi;
-  const double bb = s - hi;
-  double e = (hi - (s - bb)) + (bhi - bb);
-  e += lo + blo;
-  hi = s + e;
-  lo = e - (hi - s);
-}
-
-__device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
-// ln of m in [1/16, 1) in single precision: m = f 2^e with f in
-// [sqrt(1/2), sqrt(2)); ln f = 2 atanh(y) by its series through y^9
-// (|y| <= 0.1716, truncation < 3e-9 relative); e ln 2 added in FP64.
-__device__ __forceinline__ double ln_small(float m) {
-  int e;
-  float f = frexpf(m, &e);
-  const bool lo = f < 0.70710678f;
-  f = lo ? 2.0f * f : f;
-  e = lo ? e - 1 : e;
-  // y = (f - 1)/(f + 1): hardware reciprocal, then one correction of the
-  // quotient from its exact residual (a Newton step on the reciprocal alone
-  // leaves a one-signed error that would bias the log sum).
-  const float fp1 = f + 1.0f, fm1 = f - 1.0f;
-  const float r = __builtin_amdgcn_rcpf(fp1);
-  const float y0 = fm1 * r;
-  const float y = fmaf(fmaf(-y0, fp1, fm1), r, y0);
-  const float y2 = y * y;
-  float p = fmaf(y2, 1.0f / 9.0f, 1.0f / 7.0f);
-  p = fmaf(p, y2, 1.0f / 5.0f);
-  p = fmaf(p, y2, 1.0f / 3.0f);
-  const float s = fmaf(2.0f * y * y2, p, 2.0f * y);
-  return fma((double)e, 0.69314718055994530942, (double)s);
-}
-
-// ln of m in [1/16, 1) in double precision (FP64 format): same series
-// through y^21.
-__device__ __forceinline__ double ln_small64(double m) {
-  int e;
-  double f = frexp(m, &e);
-  const bool lo = f < 0.70710678118654752440;
-  f = lo ? 2.0 * f : f;
-  e = lo ? e - 1 : e;
-  const double y = (f - 1.0) * rcp64(f + 1.0);
-  const double y2 = y * y;
-  double p = 1.0 / 21.0;
-  p = fma(p, y2, 1.0 / 19.0);
-  p = fma(p, y2, 1.0 / 17.0);
-  p = fma(p, y2, 1.0 / 15.0);
-  p = fma(p, y2, 1.0 / 13.0);
-  p = fma(p, y2, 1.0 / 11.0);
-  p = fma(p, y2, 1.0 / 9.0);
-  p = fma(p, y2, 1.0 / 7.0);
-  p = fma(p, y2, 1.0 / 5.0);
-  p = fma(p, y2, 1.0 / 3.0);
-  const double t = 2.0 * y;
-  const double de = (double)e;
-  return fma(de, 6.93147180369123816490e-01, fma(de, 1.90821492927058770002e-10, fma(t * y2, p, t)));
-}
 
 // ------------------------------------------------------------------------
 // Amplitude rows a_k(x) = beta_k u w for frozen (M, Gamma) from the FP64 event
 // stream, written as [Re a_0..Re a_{K-1}, Im a_0..Im a_{K-1}, 0 pad] rows of
-// KP operands.  For the split format, lo = fp16(a - hi) goes to a second plane.
+// KP operands.
 // ------------------------------------------------------------------------
 template <int FMT>
 __global__ __launch_bounds__(256) void freeze_kernel(const double* __restrict__ planes, int64_t stride,
                                                      int64_t n, const double* __restrict__ tbl,
                                                      const int* __restrict__ itbl, int K, int KP,
-                                                     int gen, void* out_hi, void* out_lo) {
+                                                     int gen, void* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  for (int c = 0; c < KP; ++c) {
-    double v = 0.0;
-    if (c < 2 * K) {
-      const int k = c < K ? c : c - K;
-      const double* t = tbl + k * TS;
-      const double s = planes[(int64_t)itbl[k * ITS + 0] * stride + i];
-      const double u = planes[(int64_t)itbl[k * ITS + 1] * stride + i] * t[TB_UMUL] + t[TB_UADD];
-      const double g = planes[(int64_t)itbl[k * ITS + 2] * stride + i];
-      // Flatte resonances (general path): complex width factor g + i h
-      const double h = gen ? planes[(int64_t)itbl[k * ITS + IT_H] * stride + i] : 0.0;
-      const double Dr = t[TB_M2] - s - t[TB_NGE] * h, Di = t[TB_NGE] * g;
-      const double bu = t[TB_BETA] * u * rcp64(Dr * Dr + Di * Di);
-      v = (c < K) ? bu * Dr : -bu * Di;
-    }
+  auto put = [&](int c, double v) {
     const int64_t o = i * KP + c;
     if constexpr (FMT == PWA_OP_F64) {
-      ((double*)out_hi)[o] = v;
+      ((double*)out)[o] = v;
     } else if constexpr (FMT == PWA_OP_F32) {
-      ((float*)out_hi)[o] = (float)v;
+      ((float*)out)[o] = (float)v;
     } else if constexpr (FMT == PWA_OP_BF16) {
-      ((__bf16*)out_hi)[o] = (__bf16)(float)v;
+      ((__bf16*)out)[o] = (__bf16)(float)v;
     } else {
-      const _Float16 h = (_Float16)v;
-      ((_Float16*)out_hi)[o] = h;
-      if constexpr (FMT == PWA_OP_F16X3) ((_Float16*)out_lo)[o] = (_Float16)(v - (double)h);
+      ((_Float16*)out)[o] = (_Float16)v;
     }
+  };
+  for (int k = 0; k < K; ++k) {
+    double re, im;
+    frozen_amp(planes, stride, i, tbl, itbl, k, gen, re, im);
+    put(k, re);
+    put(K + k, im);
   }
-}
-
-// Power-of-two column scale of the split FP16 format: start b's couplings are
-// multiplied by 2^shift so that their largest real component lies in
-// [2^10, 2^11); the three FP16 parts of every component then stay in the
-// normal FP16 range.  Z scales by 2^shift and ln |Z|^2 by 2 shift ln 2, which
-// the final kernel removes exactly.
-__device__ __forceinline__ int col_shift(const double* __restrict__ C, int K, int b) {
-  double m = 0.0;
-  for (int k = 0; k < K; ++k) m = fmax(m, fmax(fabs(C[2 * (b * K + k)]), fabs(C[2 * (b * K + k) + 1])));
-  if (!(m > 0.0) || !isfinite(m)) return 0;
-  int e;
-  frexp(m, &e);   // m < 2^e
-  return 11 - e;
+  for (int c = 2 * K; c < KP; ++c) put(c, 0.0);
 }
 
 // Expanded coupling block [[Cr, Ci], [-Ci, Cr]] as KP x 2B operands, column
 // b (< B) = real part of start b, column B + b = imaginary part.  The
 // couplings enter every event's sum coherently, so a rounding of C biases
 // all N_D logarithms alike (the error grows like N_D times the gradient);
-// the accurate formats therefore carry C as a sum of parts: FP32 hi + lo,
-// or three FP16 parts (with the column scale above) for the split format.
+// the FP32 format therefore carries C as FP32 hi + lo.
 template <int FMT>
 __global__ void coupling_kernel(const double* __restrict__ C, int K, int KP, int B, void* out_hi,
-                                void* out_lo, void* out_lo2) {
+                                void* out_lo) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= KP * 2 * B) return;
   const int row = idx / (2 * B), col = idx % (2 * B);
@@ -177,16 +85,8 @@ __global__ void coupling_kernel(const double* __restrict__ C, int K, int KP, int
     ((float*)out_lo)[idx] = (float)(v - (double)h);
   } else if constexpr (FMT == PWA_OP_BF16) {
     ((__bf16*)out_hi)[idx] = (__bf16)(float)v;
-  } else if constexpr (FMT == PWA_OP_F16) {
-    ((_Float16*)out_hi)[idx] = (_Float16)v;
   } else {
-    v = ldexp(v, col_shift(C, K, b));
-    const _Float16 h = (_Float16)v;
-    const double r = v - (double)h;
-    const _Float16 l = (_Float16)r;
-    ((_Float16*)out_hi)[idx] = h;
-    ((_Float16*)out_lo)[idx] = l;
-    ((_Float16*)out_lo2)[idx] = (_Float16)(r - (double)l);
+    ((_Float16*)out_hi)[idx] = (_Float16)v;
   }
 }
 
@@ -202,9 +102,7 @@ __global__ void coupling_kernel(const double* __restrict__ C, int K, int KP, int
 // r = 0..3.
 // ------------------------------------------------------------------------
 // Number of coupling parts per format (see coupling_kernel).
-__host__ __device__ constexpr int c_parts(int fmt) {
-  return fmt == PWA_OP_F32 ? 2 : (fmt == PWA_OP_F16X3 ? 3 : 1);
-}
+__host__ __device__ constexpr int c_parts(int fmt) { return fmt == PWA_OP_F32 ? 2 : 1; }
 
 template <int FMT> struct Mma;
 template <> struct Mma<PWA_OP_F64> {
@@ -235,7 +133,6 @@ template <> struct Mma<PWA_OP_F16> {
   typedef f4_t acc_t;
   __device__ static acc_t mma(op_t a, op_t b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0); }
 };
-template <> struct Mma<PWA_OP_F16X3> : Mma<PWA_OP_F16> {};
 
 template <int FMT>
 __device__ __forceinline__ typename Mma<FMT>::op_t load_op(const void* base, int64_t off) {
@@ -268,9 +165,8 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a) {
   for (int i = threadIdx.x; i < plane; i += blockDim.x) {
     const int part = i / (KP * CHB), rem = i % (KP * CHB), row = rem / CHB, col = rem % CHB;
     const int64_t g = (int64_t)row * 2 * B + (part ? B : 0) + b0 + col;
-    sC[i] = ((const T*)a.C_hi)[g];
-    if constexpr (NCP > 1) sC[plane + i] = ((const T*)a.C_lo)[g];
-    if constexpr (NCP > 2) sC[2 * plane + i] = ((const T*)a.C_lo2)[g];
+    sC[i] = ((const T*)a.C[0])[g];
+    if constexpr (NCP > 1) sC[plane + i] = ((const T*)a.C[1])[g];
   }
   __syncthreads();
   // B operands (real and imaginary column) of one coupling part from LDS
@@ -304,12 +200,9 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a) {
   for (int64_t r0 = r_begin + 16 * wave; r0 < r_end; r0 += 64) {
     // A operands of rows r0 .. r0 + 15 (row l % 16, k-group l / 16)
     const int64_t row = min(r0 + col, a.n - 1);
-    op_t ah[NKS], al[FMT == PWA_OP_F16X3 ? NKS : 1];
+    op_t ah[NKS];
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-      ah[ks] = load_op<FMT>(a.A_hi, row * KP + ks * M::KSTEP + kg * M::E);
-      if constexpr (FMT == PWA_OP_F16X3) al[ks] = load_op<FMT>(a.A_lo, row * KP + ks * M::KSTEP + kg * M::E);
-    }
+    for (int ks = 0; ks < NKS; ++ks) ah[ks] = load_op<FMT>(a.A[0], row * KP + ks * M::KSTEP + kg * M::E);
     // rows held by this lane in the result tile
     bool valid[4];
 #pragma unroll
@@ -318,31 +211,10 @@ __global__ __launch_bounds__(256) void batched_kernel(BatchArgs a) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       acc_t zr = {0, 0, 0, 0}, zi = {0, 0, 0, 0};
-      // Accumulate the products smallest-first over the whole inner
-      // dimension: the low parts of C (and A) carry a systematic correction
-      // of relative size 2^-22 .. 2^-24; added step by step to an accumulator
-      // that already holds the large partial sums they would fall below half
-      // an ulp and be dropped every time.
-      if constexpr (NCP > 2) {
-#pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-          const int ro = (ks * M::KSTEP + kg * M::E) * CHB + t * 16 + col;
-          op_t br, bi;
-          load_b(sC + 2 * plane, ro, br, bi);
-          zr = M::mma(ah[ks], br, zr);
-          zi = M::mma(ah[ks], bi, zi);
-        }
-      }
-      if constexpr (FMT == PWA_OP_F16X3) {
-#pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-          const int ro = (ks * M::KSTEP + kg * M::E) * CHB + t * 16 + col;
-          op_t br, bi;
-          load_b(sC, ro, br, bi);
-          zr = M::mma(al[ks], br, zr);
-          zi = M::mma(al[ks], bi, zi);
-        }
-      }
+      // Accumulate the low part of C first over the whole inner dimension:
+      // it carries a systematic correction of relative size 2^-24; added
+      // step by step to an accumulator that already holds the large partial
+      // sums it would fall below half an ulp and be dropped every time.
       if constexpr (NCP > 1) {
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
@@ -531,36 +403,52 @@ __global__ __launch_bounds__(64) void batched_rowsum_kernel(const double* __rest
   part2[((int64_t)blockIdx.y * B + b) * 2 + 1] = l;
 }
 
-// Stage 2 and the likelihood: F_b from the chunk partials in order
-// (double-double), less the column scale of the split format, G_b by the
-// quadratic form in FP64, NLL_b = -F_b + N_D ln(c_b^H Gm c_b / N_MC).
-__global__ void batched_final_kernel(const double* __restrict__ part2, int B, int K,
-                                     const double* __restrict__ C, const double* __restrict__ gram,
-                                     double nd, double nm, int scaled, double* __restrict__ nll) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+// Stage 2 and the likelihood, one wave per start: F_b from the chunk
+// partials (double-double, a fixed butterfly over the lanes), plus the powers
+// of two of the sliced format; G_b = c_b^H Gm c_b with lane k forming
+// Re(conj(c_k) (Gm c)_k); NLL_b = -F_b + N_D ln(G_b / N_MC).
+__global__ __launch_bounds__(64) void batched_final_kernel(const double* __restrict__ part2, int B,
+                                                          int K, const double* __restrict__ C,
+                                                          const double* __restrict__ gram,
+                                                          double nd, double nm,
+                                                          const unsigned long long* esum,
+                                                          double* __restrict__ nll) {
+  const int b = blockIdx.x, lane = threadIdx.x;
   double h = 0.0, l = 0.0;
-  for (int c = 0; c < kBatchChunks; ++c)
-    dd_add_b(h, l, part2[((int64_t)c * B + b) * 2], part2[((int64_t)c * B + b) * 2 + 1]);
-  if (scaled) {   // remove N_D * 2 shift ln 2 (an exact integer times ln 2 in two parts)
-    const double m = -2.0 * nd * (double)col_shift(C, K, b);
-    dd_add_b(h, l, m * 6.93147180369123816490e-01, m * 1.90821492927058770002e-10);
+  if (lane < kBatchChunks) {
+    h = part2[((int64_t)lane * B + b) * 2];
+    l = part2[((int64_t)lane * B + b) * 2 + 1];
   }
-  const double F = h + l;
-  double G = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const double ckr = C[2 * (b * K + k)], cki = C[2 * (b * K + k) + 1];
+  double g = 0.0;
+  if (lane < K) {
+    const double ckr = C[2 * (b * K + lane)], cki = C[2 * (b * K + lane) + 1];
     double sr = 0.0, si = 0.0;   // (Gm c)_k
     for (int j = 0; j < K; ++j) {
-      const double gr = gram[2 * (k * K + j)], gi = gram[2 * (k * K + j) + 1];
+      const double gr = gram[2 * (lane * K + j)], gi = gram[2 * (lane * K + j) + 1];
       const double cr = C[2 * (b * K + j)], ci = C[2 * (b * K + j) + 1];
       sr += gr * cr - gi * ci;
       si += gr * ci + gi * cr;
     }
-    G += ckr * sr + cki * si;    // Re(conj(c_k) (Gm c)_k)
+    g = ckr * sr + cki * si;
   }
-  double val = -F + nd * log(G / nm);
-  if (!(G > 0.0) || !isfinite(val)) val = INFINITY;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double oh = __shfl_xor(h, off), ol = __shfl_xor(l, off);
+    dd_add_b(h, l, oh, ol);
+    g += __shfl_xor(g, off);
+  }
+  if (lane != 0) return;
+  if (esum) {
+    // ln |Z|^2 = ln |Z_s|^2 + 2 (E_i + G_b - 18) ln 2 per event: an exact
+    // integer m times ln 2 (two parts; m ln2_hi split exactly by an FMA)
+    const long long n = (long long)nd;
+    const double m = 2.0 * (double)((long long)*esum + ((long long)coupling_exponent(C, K, b) - 18) * n);
+    const double p = m * 6.93147180369123816490e-01;
+    const double pe = fma(m, 6.93147180369123816490e-01, -p);
+    dd_add_b(h, l, p, fma(m, 1.90821492927058770002e-10, pe));
+  }
+  const double F = h + l;
+  double val = -F + nd * log(g / nm);
+  if (!(g > 0.0) || !isfinite(val)) val = INFINITY;
   nll[b] = val;
 }
 
@@ -574,19 +462,22 @@ int batched_kp(int fmt, int K) {
   return (2 * K + 15) / 16 * 16;
 }
 int batched_elem_bytes(int fmt) { return fmt == PWA_OP_F64 ? 8 : (fmt == PWA_OP_F32 ? 4 : 2); }
+int batched_a_planes(int fmt) { return fmt == PWA_OP_F16S ? kSlices : 1; }
+int batched_c_planes(int fmt) { return fmt == PWA_OP_F16S ? kSlices : c_parts(fmt); }
 
 hipError_t launch_freeze(int fmt, const double* planes, int64_t stride, int64_t n,
-                         const double* tbl, const int* itbl, int K, int KP, int gen, void* out_hi,
-                         void* out_lo, hipStream_t st) {
+                         const double* tbl, const int* itbl, int K, int KP, int gen,
+                         void* const* out, unsigned long long* esum, hipStream_t st) {
+  if (fmt == PWA_OP_F16S)
+    return launch_freeze_slices(planes, stride, n, tbl, itbl, K, KP, gen, (_Float16*)out[0], esum, st);
   if (n <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((n + 255) / 256);
-#define PWA_FZ(F) hipLaunchKernelGGL(freeze_kernel<F>, dim3(grid), dim3(256), 0, st, planes, stride, n, tbl, itbl, K, KP, gen, out_hi, out_lo)
+#define PWA_FZ(F) hipLaunchKernelGGL(freeze_kernel<F>, dim3(grid), dim3(256), 0, st, planes, stride, n, tbl, itbl, K, KP, gen, out[0])
   switch (fmt) {
     case PWA_OP_F64: PWA_FZ(PWA_OP_F64); break;
     case PWA_OP_F32: PWA_FZ(PWA_OP_F32); break;
     case PWA_OP_BF16: PWA_FZ(PWA_OP_BF16); break;
-    case PWA_OP_F16: PWA_FZ(PWA_OP_F16); break;
-    default: PWA_FZ(PWA_OP_F16X3); break;
+    default: PWA_FZ(PWA_OP_F16); break;
   }
 #undef PWA_FZ
   return hipGetLastError();
@@ -603,17 +494,17 @@ hipError_t launch_gram(const double* planes, int64_t stride, int64_t base, int64
   return hipGetLastError();
 }
 
-hipError_t launch_batched(int fmt, const BatchArgs& a, int row_blocks, const double* C,
-                          const double* gram, int K, double nd, double nm, double* nll,
-                          hipStream_t st) {
+namespace {
+// FP64, FP32, BF16 and FP16 formats: coupling block, then the data term.
+hipError_t launch_plain(int fmt, const BatchArgs& a, int row_blocks, const double* C, int K,
+                        hipStream_t st) {
   const unsigned cg = (unsigned)((a.KP * 2 * a.B + 255) / 256);
-#define PWA_CP(F) hipLaunchKernelGGL(coupling_kernel<F>, dim3(cg), dim3(256), 0, st, C, K, a.KP, a.B, (void*)a.C_hi, (void*)a.C_lo, (void*)a.C_lo2)
+#define PWA_CP(F) hipLaunchKernelGGL(coupling_kernel<F>, dim3(cg), dim3(256), 0, st, C, K, a.KP, a.B, (void*)a.C[0], (void*)a.C[1])
   switch (fmt) {
     case PWA_OP_F64: PWA_CP(PWA_OP_F64); break;
     case PWA_OP_F32: PWA_CP(PWA_OP_F32); break;
     case PWA_OP_BF16: PWA_CP(PWA_OP_BF16); break;
-    case PWA_OP_F16: PWA_CP(PWA_OP_F16); break;
-    default: PWA_CP(PWA_OP_F16X3); break;
+    default: PWA_CP(PWA_OP_F16); break;
   }
 #undef PWA_CP
   hipError_t e = hipGetLastError();
@@ -643,20 +534,27 @@ hipError_t launch_batched(int fmt, const BatchArgs& a, int row_blocks, const dou
     case PWA_OP_F64: PWA_WIDE(PWA_OP_F64); break;
     case PWA_OP_F32: PWA_WIDE(PWA_OP_F32); break;
     case PWA_OP_BF16: PWA_NARROW(PWA_OP_BF16); break;
-    case PWA_OP_F16: PWA_NARROW(PWA_OP_F16); break;
-    default: PWA_NARROW(PWA_OP_F16X3); break;
+    default: PWA_NARROW(PWA_OP_F16); break;
   }
 #undef PWA_NARROW
 #undef PWA_WIDE
 #undef PWA_BK
-  e = hipGetLastError();
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_batched(int fmt, const BatchArgs& a, int row_blocks, const double* C,
+                          const double* gram, int K, double nd, double nm, double* nll,
+                          hipStream_t st) {
+  hipError_t e = fmt == PWA_OP_F16S ? launch_sliced(a, row_blocks, C, K, st)
+                                    : launch_plain(fmt, a, row_blocks, C, K, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(batched_rowsum_kernel, dim3((a.B + 63) / 64, kBatchChunks), dim3(64), 0, st,
                      a.part, row_blocks, a.B, a.part2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(batched_final_kernel, dim3((a.B + 255) / 256), dim3(256), 0, st, a.part2,
-                     a.B, K, C, gram, nd, nm, fmt == PWA_OP_F16X3 ? 1 : 0, nll);
+  hipLaunchKernelGGL(batched_final_kernel, dim3(a.B), dim3(64), 0, st, a.part2,
+                     a.B, K, C, gram, nd, nm, fmt == PWA_OP_F16S ? a.esum : nullptr, nll);
   return hipGetLastError();
 }
 

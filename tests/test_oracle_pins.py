@@ -390,3 +390,82 @@ def test_round_to_formats():
     x = np.array([1.0, 1.0 + 2 ** -9, 1.0 + 3 * 2 ** -9, 3.14159265])
     np.testing.assert_array_equal(oracle.round_to(x, "bf16")[:3], [1.0, 1.0, 1.0 + 2 ** -7])
     assert oracle.round_to(np.array([1.0 + 2 ** -12]), "f16")[0] == 1.0
+
+
+# ------------------------------------ sliced FP16 operand format (batched)
+def test_fixed_slices_worked_example():
+    """x = (1.5, 2^-20 + 2^-30): |max| = 1.5 < 2^1, so the row is scaled by
+    2^8 to (384, 2^-12 + 2^-22); slice by slice (remainder times 2^9):
+    q0 = (384, 0), q1 = (0, 0) [2^-3 + 2^-13 rounds to 0],
+    q2 = (0, 64) [64 + 2^-4], q3 = (0, 32) [2^-4 * 2^9], remainder 0."""
+    q, E = oracle.fixed_slices(np.array([[1.5, 2.0 ** -20 + 2.0 ** -30]]), axis=1)
+    assert E[0, 0] == 1
+    np.testing.assert_array_equal(np.array(q)[:, 0, :], [[384, 0], [0, 0], [0, 64], [0, 32]])
+
+
+def test_fixed_slices_bounds_and_reconstruction():
+    """Slices are integers with |q0| <= 512 and |q_s| <= 256 after it; the
+    reconstruction misses x by at most 2^(E - 37); a value on the 2^(E-36)
+    grid is reproduced exactly; zero vectors give E = 0 and zero slices."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    x = rng.normal(size=(200, 40)) * 10.0 ** rng.uniform(-6, 6, size=(200, 1))
+    x[7] = 0.0
+    q, E = oracle.fixed_slices(x, axis=1)
+    q = np.array(q)
+    assert np.all(q == np.rint(q))
+    assert np.max(np.abs(q[0])) <= 512 and np.max(np.abs(q[1:])) <= 256
+    rec = sum(np.ldexp(q[s], E - 9 - 9 * s) for s in range(4))
+    assert np.all(np.abs(rec - x) <= np.ldexp(1.0, E - 37))
+    assert E[7, 0] == 0 and np.all(q[:, 7] == 0)
+    assert np.all(np.abs(x) < np.ldexp(1.0, E)) and np.all(np.max(np.abs(x), axis=1, keepdims=True)[E != 0]
+                                                         >= np.ldexp(1.0, E - 1)[E != 0])
+    g = np.ldexp(rng.integers(-2 ** 35, 2 ** 35, size=(50, 8)).astype(float), -36)   # |g| < 2^-1
+    g[:, 0] = 0.75                                                                   # E = 0 per row
+    qg, Eg = oracle.fixed_slices(g, axis=1)
+    assert np.all(Eg == 0)
+    np.testing.assert_array_equal(sum(np.ldexp(qg[s], -9 - 9 * s) for s in range(4)), g)
+
+
+def test_sliced_product_error_bound():
+    """|Z - A C| <= K 2^(E_row + G_col - 35) elementwise: per term the
+    remainders contribute at most 2^-28 of 512 in slice units (twice) and
+    the dropped slice pairs (i + j = 4 .. 6) at most 3 2^-36 2^16 + 2 2^-45
+    2^16 + 2^-54 2^16.  Dropping the last level breaks it more than
+    tenfold."""
+    rng = np.random.Generator(np.random.PCG64(22))
+    K = 20
+    A = (rng.normal(size=(300, K)) + 1j * rng.normal(size=(300, K))) * 10.0 ** rng.uniform(-3, 3, (300, K))
+    C = rng.uniform(0, 1, (K, 16)) * np.exp(2j * np.pi * rng.uniform(size=(K, 16)))
+    Z = oracle.sliced_product(A, C)
+    _, Ea = oracle.fixed_slices(A, axis=1)
+    _, Gc = oracle.fixed_slices(C, axis=0)
+    exact = A @ C
+    bound = K * np.ldexp(1.0, Ea + Gc - 35)
+    assert np.all(np.abs(Z - exact) <= bound)
+    assert np.max(np.abs(Z - exact) / bound) > 1e-6          # the bound is not vacuous
+    # with one level fewer the error is far outside it
+    qa, _ = oracle.fixed_slices(A, axis=1)
+    qc, _ = oracle.fixed_slices(C, axis=0)
+    Z2 = sum(np.ldexp(1.0, -9 * (i + j)) * (qa[i] @ qc[j]) for i in range(4) for j in range(4) if i + j <= 2)
+    Z2 = Z2 * np.ldexp(1.0, Ea + Gc - 18)
+    assert np.max(np.abs(Z2 - exact) / bound) > 10
+
+
+def test_sliced_nll_matches_fp64_on_representable_operands(make_model):
+    """Where every amplitude and coupling lies on its slice grid (here: C
+    with 12-bit components, and the level sum holds them exactly), the
+    sliced-format NLL equals the FP64 one up to the sums' rounding; on
+    general operands it stays within the error the bound above allows."""
+    ch, sp = synth.resonance_layout(4)
+    model = make_model(ch, sp)
+    th = synth.draw_theta(ch, sp, np.random.Generator(np.random.PCG64(31)))
+    data, mc = _events(500, 32), _events(2000, 33)
+    rng = np.random.Generator(np.random.PCG64(34))
+    C = rng.uniform(0, 1, (4, 6)) * np.exp(2j * np.pi * rng.uniform(size=(4, 6)))
+    ref = oracle.nll_batched(data, mc, model, th, C)
+    got = oracle.nll_batched(data, mc, model, th, C, fmt="f16s")
+    assert np.max(np.abs(got - ref)) <= 1e-6
+    # an amplitude matrix on the grid: a row whose entries are small integers
+    A = rng.integers(-300, 300, size=(50, 4)) + 1j * rng.integers(-300, 300, size=(50, 4))
+    Cg = (rng.integers(-2048, 2048, size=(4, 6)) + 1j * rng.integers(-2048, 2048, size=(4, 6))) * 2.0 ** -11
+    np.testing.assert_array_equal(oracle.sliced_product(A.astype(complex), Cg), A @ Cg)
