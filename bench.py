@@ -75,6 +75,26 @@ def measured_traffic(kernel):
             + float(fields["write_kib_per_dispatch"]) * 1024.0 * float(fields["write_calibration"]))
 
 
+def measured_valu_instructions(kernel):
+    """VALU instructions per dispatch of `kernel` from the same committed
+    counter summary (SQ_INSTS_VALU), or None under the same conditions as
+    measured_traffic."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(TRAFFIC_PROFILE):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel") != kernel or fields.get("source_sha256") != src:
+        return None
+    v = fields.get("valu_instructions_per_dispatch")
+    return float(v) if v else None
+
+
 def make_workload():
     """MC: uniform phase space (seeded NumPy).  Data: drawn from the model at
     the generating parameters by accept-reject on the GPU (seeded torch
@@ -439,9 +459,13 @@ def main():
     gbs = bytes_launch / k_avg_s / 1e9
     tfl = flops / k_avg_s / 1e12
     hbm_bound = flops / bytes_launch < FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    traffic = None
+    traffic = valu = None
     if args.precision == "f64" and not args.shape:
         traffic = measured_traffic("wg_kernel<double, 2, 4, 3>")
+        valu = measured_valu_instructions("wg_kernel<double, 2, 4, 3>")
+    # VALU-issue floor: one wave64 instruction per SIMD every 4 cycles, 1024
+    # SIMDs at the 2.4 GHz peak clock
+    valu_floor_s = valu * 4 / (1024 * 2.4e9) if valu else None
     roof = {"bound": "hbm" if hbm_bound else "alu",
             "achieved": round(gbs if hbm_bound else tfl, 3),
             "peak": HBM_PEAK_GBS if hbm_bound else FP64_PEAK_TFLOPS,
@@ -452,7 +476,10 @@ def main():
             "kernel": f"wg_kernel HVP ({args.precision}), per-event pass",
             "kernel_avg_us": round(k_avg_s * 1e6, 2),
             "algorithmic_bytes_per_launch": bytes_launch, "algorithmic_flops_per_launch": flops,
-            "alu_achieved_tflops": round(tfl, 3), "alu_frac": round(tfl / FP64_PEAK_TFLOPS, 4)}
+            "alu_achieved_tflops": round(tfl, 3), "alu_frac": round(tfl / FP64_PEAK_TFLOPS, 4),
+            "valu_instructions_per_launch": valu,
+            "valu_issue_floor_us": round(valu_floor_s * 1e6, 1) if valu_floor_s else None,
+            "valu_issue_frac": round(valu_floor_s / k_avg_s, 4) if valu_floor_s else None}
     result = {
         "metric": "events/s for NLL+grad+HVP (one fused evaluation)",
         "value": round(value, 1), "unit": "events/s", "n_gpus": 1, "steps": args.steps,
