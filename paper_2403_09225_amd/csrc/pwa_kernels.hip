@@ -115,6 +115,10 @@ __device__ __forceinline__ void acc_add(double& acc, double x) { acc += x; }
 __device__ __forceinline__ void acc_add(double& acc, float x) { acc += (double)x; }
 __device__ __forceinline__ void acc_fma(double& acc, double a, double b) { acc = fma(a, b, acc); }
 __device__ __forceinline__ void acc_fma(double& acc, float a, float b) { acc += (double)(a * b); }
+// FP32 run accumulators (FP32 stream, wave-group pass): a few batches of
+// per-event terms summed in FP32, then flushed into the FP64 accumulators.
+__device__ __forceinline__ void acc_add(float& acc, float x) { acc += x; }
+__device__ __forceinline__ void acc_fma(float& acc, float a, float b) { acc = fmaf(a, b, acc); }
 __device__ __forceinline__ float log_r(float x) { return __logf(x); }
 
 // Double-double accumulation (TwoSum then renormalise).  Symmetric in its
@@ -835,6 +839,31 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
   double acc[NA > 0 ? NA : 1];
 #pragma unroll
   for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+  // With the FP32 stream the moments of kRun batches are summed in FP32 run
+  // accumulators and then added to the FP64 ones: one FP32 add per term
+  // instead of a conversion and an FP64 add (a run of 8 per-lane terms costs
+  // at most a few FP32 roundings, far inside the stream's own 2^-24).  Only
+  // up to 3 resonances per wave and 8 waves per block: beyond that the extra
+  // registers would spill.
+  constexpr bool RUN = sizeof(Real) == 4 && NA <= 3 * NMOM_HVP && G <= 8;
+  constexpr int kRun = 8;
+  typedef typename std::conditional<RUN, float, double>::type AccR;
+  AccR racc[RUN && NA > 0 ? NA : 1];
+#pragma unroll
+  for (int j = 0; j < (RUN ? NA : 0); ++j) racc[j] = 0.f;
+  AccR* const macc = [&]() -> AccR* {
+    if constexpr (RUN) return racc;
+    else return acc;
+  }();
+  auto flush = [&]() {
+    if constexpr (RUN) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        acc[j] += (double)racc[j];
+        racc[j] = 0.f;
+      }
+    }
+  };
 
   const int nbat = (int)((rg.end - rg.begin + 63) / 64);
   if (nbat > 0) {
@@ -1041,7 +1070,7 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
         for (int r = 0; r < R; ++r) {
           const Real wr = cwr[r], wi = cwi[r], g = gc[r];
           const Real uwr = cu[r] * wr, uwi = cu[r] * wi;
-          double* m = acc + NM * r;
+          AccR* m = macc + NM * r;
           const Real ar_ = alr * uwr - ali * uwi, ai_ = alr * uwi + ali * uwr;
           const Real br_ = ar_ * wr - ai_ * wi, bi_ = ar_ * wi + ai_ * wr;
           acc_add(m[0], ar_);
@@ -1059,7 +1088,7 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
           __builtin_amdgcn_sched_barrier(0);
           const Real wr = cwr[r], wi = cwi[r], g = gc[r];
           const Real uwr = cu[r] * wr, uwi = cu[r] * wi;
-          double* m = acc + NM * r;
+          AccR* m = macc + NM * r;
           const Real pr = gr * uwr - gi * uwi, pi = gr * uwi + gi * uwr;
           const Real qr = pr * wr - pi * wi, qi = pr * wi + pi * wr;
           acc_add(m[0], pr);
@@ -1095,8 +1124,12 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
       stage = (stage == NSTAGE - 1) ? 0 : stage + 1;
       buf ^= 1;
     };
-    for (int b = 0; b < nbat - 1; ++b) step(b, std::false_type{});
+    for (int b = 0; b < nbat - 1; ++b) {
+      step(b, std::false_type{});
+      if (RUN && (b % kRun) == kRun - 1) flush();
+    }
     step(nbat - 1, std::true_type{});
+    flush();
   }
 
   // ---- reduction: each wave owns its resonances, so a wave-level
