@@ -23,6 +23,7 @@ onto [-1, 1].
 """
 
 import ctypes
+import math
 import os
 import time
 
@@ -449,7 +450,39 @@ class ToyStudy:
                 summary[f"{name}_success_rate"] = float(np.mean([r[f"{name}_success"] for r in rows]))
                 summary[f"mean_iterations_{name}_strategy"] = float(np.mean([r[f"{name}_iterations"] for r in rows]))
                 summary[f"mean_seconds_{name}_strategy"] = float(np.mean([r[f"{name}_seconds"] for r in rows]))
+        if "blind_success" in rows[0]:
+            summary["proposal_vs_blind"] = paired_comparison(rows, "proposal", "blind")
         return summary, rows
+
+
+def sign_test(n_a, n_b):
+    """Two-sided exact sign test on n_a + n_b discordant pairs (n_a where
+    only the first strategy succeeds, n_b where only the second does)."""
+    n = n_a + n_b
+    if n == 0:
+        return 1.0
+    k = min(n_a, n_b)
+    tail = sum(math.comb(n, j) for j in range(k + 1)) / 2.0 ** n
+    return min(1.0, 2.0 * tail)
+
+
+def paired_comparison(rows, a, b):
+    """Per-toy comparison of two single-start strategies on the same toys:
+    the discordant successes with an exact sign test, and the per-toy
+    difference of expected Newton iterations to the global minimum with a
+    Wilcoxon signed-rank test (scipy)."""
+    sa = np.array([r[f"{a}_success"] for r in rows], dtype=bool)
+    sb = np.array([r[f"{b}_success"] for r in rows], dtype=bool)
+    n_a, n_b = int(np.sum(sa & ~sb)), int(np.sum(~sa & sb))
+    d = np.array([r[f"{a}_iterations"] - r[f"{b}_iterations"] for r in rows], dtype=np.float64)
+    p_w = 1.0
+    if np.any(d != 0):
+        from scipy.stats import wilcoxon
+        p_w = float(wilcoxon(d, zero_method="wilcox", alternative="two-sided").pvalue)
+    return {"toys": len(rows), "both": int(np.sum(sa & sb)), "neither": int(np.sum(~sa & ~sb)),
+            f"only_{a}": n_a, f"only_{b}": n_b, "sign_test_p": sign_test(n_a, n_b),
+            "mean_iteration_difference": float(np.mean(d)),
+            "median_iteration_difference": float(np.median(d)), "wilcoxon_p": p_w}
 
 
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
@@ -499,7 +532,21 @@ def main(argv=None):
                     "to this .npz")
     ap.add_argument("--save-set", default="", help="save the training features (one row per "
                     "toy, float16) and labels to this .npz")
+    ap.add_argument("--evaluate-shipped", action="store_true",
+                    help="only evaluate the shipped proposal (data/) on --eval fresh toys of "
+                    "--eval-events events, seeded by --seed")
     a = ap.parse_args(argv)
+    if a.evaluate_shipped:
+        net, prior, blind, meta = load_proposal()
+        ch, sp = resonance_layout(int(meta["K"]))
+        ev = ToyStudy(ch, sp, a.mc, prior=prior, seed=a.seed)
+        summary, rows = ev.evaluate(net, a.eval, a.eval_events, a.random,
+                                    log_every=max(1, min(10, a.eval // 10)), blind=blind)
+        print(json.dumps(summary), flush=True)
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump({"summary": summary, "rows": rows}, f, indent=1)
+        return summary
     ch, sp = resonance_layout(a.K)
     if a.m_spread > 0:
         # the analysis model: nominal masses and widths drawn once from the wide prior

@@ -4,13 +4,18 @@ The K = 12 proposal shipped with the package (trained by
 `python -m paper_2403_09225_amd.learned_start` on 4500 toy fits) is run on
 fresh toys drawn from its prior (a seed it was not trained or validated on).
 Per toy, Newton-CG is started from the truth, from the proposal, from the
-blind start (the mean training label, which ignores the data) and from 8
+blind start (the mean training label, which ignores the data) and from 4
 random draws of the prior; the global minimum is the lowest NLL among them
 and a fit succeeds within 0.01 of it.
 
-Checked: the proposal succeeds more often than a random start, and the
-proposal strategy (its fit, then random starts if it fails) reaches the
-global minimum in fewer expected Newton iterations than random multi-start.
+Checked on 96 toys: the proposal succeeds more often than a random start;
+the proposal strategy (its fit, then random starts if it fails) reaches the
+global minimum in fewer expected Newton iterations than random multi-start;
+and, toy by toy, the proposal beats the blind start: among the toys where
+exactly one of the two succeeds, the proposal's share is significant under
+an exact two-sided sign test (p < 0.01).  A network that had learned only
+the prior mean would be the blind start and fail the last check.  (On 300
+toys of the same kind the split was 96 : 35, p = 9e-8.)
 """
 
 import sys
@@ -25,15 +30,18 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def test_proposal_beats_random_multistart():
+def test_proposal_beats_random_multistart_and_the_blind_start():
     from paper_2403_09225_amd.learned_start import ToyStudy, load_proposal, resonance_layout
     net, prior, blind, meta = load_proposal()
     K = int(meta["K"])
     ch, sp = resonance_layout(K)
     say(f"[learned start] K = {K}, proposal trained on {int(meta['train_toys'])} toys")
     study = ToyStudy(ch, sp, 200_000, prior=prior, seed=2024)
-    summary, rows = study.evaluate(net, n_toys=24, n_events=20_000, n_random=8, blind=blind,
-                                   log_every=4)
+    summary, rows = study.evaluate(net, n_toys=96, n_events=20_000, n_random=4, blind=blind,
+                                   log_every=8)
     say(f"[learned start] {summary}")
     assert summary["proposal_success_rate"] > summary["random_start_success_rate"]
     assert summary["mean_iterations_proposal_strategy"] < summary["mean_iterations_random_strategy"]
+    pb = summary["proposal_vs_blind"]
+    assert pb["only_proposal"] > pb["only_blind"], pb
+    assert pb["sign_test_p"] < 0.01, pb
