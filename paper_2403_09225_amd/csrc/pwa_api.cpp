@@ -56,6 +56,7 @@ struct pwa_ctx {
   double* bpart = nullptr;
   double* bpart2 = nullptr;
   double* bgram_part = nullptr;
+  double* bgram_xtx = nullptr;
   double* bgram = nullptr;
   // kernel timing
   bool timing = false;
@@ -1230,11 +1231,11 @@ int pwa_fit_bfgs(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_rep
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int kBatchRowBlocks = 2048;
-constexpr int kGramBlocks = 512;
+constexpr int kGramBlocks = 1024;   // 4 blocks per CU (37 KB of LDS each)
 constexpr int kGP = 48;
 
 struct BLayout {
-  size_t A, C, esum, part, part2, gpart, gram, total;
+  size_t A, C, esum, part, part2, gpart, xtx, gram, total;
   size_t a_plane, c_plane;   // bytes per operand plane
   int KP;
 };
@@ -1258,6 +1259,7 @@ BLayout blayout(const pwa_ctx* c, int64_t n_data, int fmt, int max_batch) {
   L.part = take(sizeof(double) * 2 * (size_t)kBatchRowBlocks * max_batch);
   L.part2 = take(sizeof(double) * 2 * (size_t)kBatchChunks * max_batch);
   L.gpart = take(sizeof(double) * 2 * (size_t)kGramBlocks * kGP * kGP);
+  L.xtx = take(sizeof(double) * (size_t)kGP * kGP);
   L.gram = take(sizeof(double) * 2 * (size_t)c->K * c->K);
   L.total = off;
   return L;
@@ -1297,6 +1299,7 @@ int pwa_freeze(pwa_ctx* c, const double* d_theta, int32_t fmt, int32_t max_batch
   c->bpart = (double*)(w + L.part);
   c->bpart2 = (double*)(w + L.part2);
   c->bgram_part = (double*)(w + L.gpart);
+  c->bgram_xtx = (double*)(w + L.xtx);
   c->bgram = (double*)(w + L.gram);
   // a multiple of 8: the sliced kernel places the chunk blocks of one row
   // block on one XCD
@@ -1309,7 +1312,7 @@ int pwa_freeze(pwa_ctx* c, const double* d_theta, int32_t fmt, int32_t max_batch
                     c->md.gen, c->bA, c->besum, st) != hipSuccess)
     return PWA_E_HIP;
   if (launch_gram(c->planes64, c->stride, c->mc_off, c->n_mc, c->tbl64, c->itbl, c->K, c->md.gen,
-                  c->bgram_blocks, c->bgram_part, c->bgram, st) != hipSuccess)
+                  c->bgram_blocks, c->bgram_part, c->bgram_xtx, c->bgram, st) != hipSuccess)
     return PWA_E_HIP;
   c->frozen = true;
   return PWA_OK;
@@ -1390,14 +1393,15 @@ int pwa_fit_fractions(pwa_ctx* c, const double* d_theta, double* d_ff, double* d
 
 // Fraction matrix: MC Gram matrix at theta's masses and widths (the batched
 // path's FP64 matrix-core Gram kernel), then the coupling contraction.
-constexpr int kPhiGramBlocks = 512;
+constexpr int kPhiGramBlocks = 1024;
 constexpr int kPhiGP = 48;   // padded 2K of the Gram kernel (K <= 24)
 
 size_t pwa_fraction_matrix_workspace_bytes(const pwa_ctx* c) {
   // the MC Gram matrix holds one amplitude row per event: spin-0 parent only
   if (!c || c->K > 24 || !(c->streams & PWA_STREAM_F64) || c->md.parent_spin != 0) return 0;
   return align_up(sizeof(double) * 2 * (size_t)kPhiGramBlocks * kPhiGP * kPhiGP, 256) +
-         align_up(sizeof(double) * 2 * (size_t)c->K * c->K, 256);
+         align_up(sizeof(double) * 2 * (size_t)c->K * c->K, 256) +
+         align_up(sizeof(double) * (size_t)kPhiGP * kPhiGP, 256);
 }
 
 int pwa_fraction_matrix(pwa_ctx* c, const double* d_theta, void* d_ws, size_t ws_bytes,
@@ -1411,11 +1415,12 @@ int pwa_fraction_matrix(pwa_ctx* c, const double* d_theta, void* d_ws, size_t ws
   double* part = (double*)d_ws;
   double* gram = (double*)((char*)d_ws +
                            align_up(sizeof(double) * 2 * (size_t)kPhiGramBlocks * kPhiGP * kPhiGP, 256));
+  double* xtx = (double*)((char*)gram + align_up(sizeof(double) * 2 * (size_t)c->K * c->K, 256));
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kPhiGramBlocks, (c->n_mc + 255) / 256));
   if (launch_table(d_theta, nullptr, c->md, c->K, c->tbl64, c->tbl32, c->itbl, c->status, st) != hipSuccess)
     return PWA_E_HIP;
   if (launch_gram(c->planes64, c->stride, c->mc_off, c->n_mc, c->tbl64, c->itbl, c->K, c->md.gen,
-                  blocks, part, gram, st) != hipSuccess)
+                  blocks, part, xtx, gram, st) != hipSuccess)
     return PWA_E_HIP;
   return launch_phi(gram, d_theta, c->K, d_phi, st) == hipSuccess ? PWA_OK : PWA_E_HIP;
 }

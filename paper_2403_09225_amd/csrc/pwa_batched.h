@@ -28,9 +28,10 @@ int batched_c_planes(int fmt);
 hipError_t launch_freeze(int fmt, const double* planes, int64_t stride, int64_t n,
                          const double* tbl, const int* itbl, int K, int KP, int gen,
                          void* const* out, unsigned long long* esum, hipStream_t st);
+// xtx: scratch of 48 x 48 doubles (the summed X^T X)
 hipError_t launch_gram(const double* planes, int64_t stride, int64_t base, int64_t n,
                        const double* tbl, const int* itbl, int K, int gen, int nblocks, double* part,
-                       double* gram, hipStream_t st);
+                       double* xtx, double* gram, hipStream_t st);
 // sliced FP16 format (pwa_sliced.hip)
 hipError_t launch_freeze_slices(const double* planes, int64_t stride, int64_t n, const double* tbl,
                                 const int* itbl, int K, int KP, int gen, _Float16* q,

@@ -299,20 +299,23 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ pl
                                                    const double* __restrict__ tbl,
                                                    const int* __restrict__ itbl, int K, int gen,
                                                    double* __restrict__ part) {
-  __shared__ double X[4][16][GP];
+  // one LDS buffer: the waves' event rows X[4][16][GP] during the pass, the
+  // block's double-double sum of X^T X after it (37 KB: 4 blocks per CU)
+  __shared__ double smem[2 * GP * GP];
+  double(*X)[16][GP] = (double(*)[16][GP])smem;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t per_block = (n + gridDim.x - 1) / gridDim.x;
   const int64_t e_begin = min(n, (int64_t)blockIdx.x * per_block);
   const int64_t e_end = min(n, e_begin + per_block);
-  d4_t acc[3][3];
+  // X^T X is symmetric: only the tiles (I, J), I <= J, are formed
+  constexpr int TI[6] = {0, 0, 0, 1, 1, 2}, TJ[6] = {0, 1, 2, 1, 2, 2};
+  d4_t acc[6];
 #pragma unroll
-  for (int I = 0; I < 3; ++I)
-#pragma unroll
-    for (int J = 0; J < 3; ++J) acc[I][J] = (d4_t){0, 0, 0, 0};
+  for (int t = 0; t < 6; ++t) acc[t] = (d4_t){0, 0, 0, 0};
   const int col = lane & 15, kg = lane >> 4;
-  for (int64_t e0 = e_begin; e0 < e_end; e0 += 64) {   // same trip count in every wave
-    // lane l computes features of event e0 + 16 wave + l % 16, resonances kg, kg + 4, ...
-    const int64_t ev = e0 + 16 * wave + col;
+  for (int64_t e0 = e_begin + 16 * wave; e0 < e_end; e0 += 64) {
+    // lane l computes features of event e0 + l % 16, resonances kg, kg + 4, ...
+    const int64_t ev = e0 + col;
     const bool valid = ev < e_end;
     for (int k = kg; k < GP / 2; k += 4) {
       double re = 0.0, im = 0.0;
@@ -334,56 +337,85 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ pl
       }
     }
     for (int c = 2 * K + kg; c < GP; c += 4) X[wave][col][c] = 0.0;
-    __syncthreads();
+    // X[wave] belongs to this wave alone and one wave's LDS operations are
+    // carried out in order, so its reads below see its writes above; the
+    // fences keep the compiler from moving LDS accesses across this point.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {   // 4 events per MFMA step
+      double v[3];
 #pragma unroll
-      for (int I = 0; I < 3; ++I) {
-        const double av = X[wave][4 * ks + kg][16 * I + col];   // (X^T)[16 I + col][event]
+      for (int I = 0; I < 3; ++I) v[I] = X[wave][4 * ks + kg][16 * I + col];   // (X^T)[16 I + col][event]
 #pragma unroll
-        for (int J = 0; J < 3; ++J) {
-          const double bv = X[wave][4 * ks + kg][16 * J + col];
-          acc[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[I][J], 0, 0, 0);
+      for (int t = 0; t < 6; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[TI[t]], v[TJ[t]], acc[t], 0, 0, 0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // block partial of X^T X: the waves add their tiles in order, wave 0
+  // first, into a double-double buffer (the tiles below the diagonal are the
+  // transposes of those above; every lane owns distinct entries)
+  __syncthreads();   // every wave is done with X
+  double* rh = smem;
+  double* rl = smem + GP * GP;
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * TI[t] + 4 * q + kg, c = 16 * TJ[t] + col;
+#pragma unroll
+          for (int m = 0; m < (TI[t] != TJ[t] ? 2 : 1); ++m) {
+            const int i = m == 0 ? r * GP + c : c * GP + r;
+            if (w == 0) {
+              rh[i] = acc[t][q];
+              rl[i] = 0.0;
+            } else {
+              double h = rh[i], l = rl[i];
+              dd_add_b(h, l, acc[t][q], 0.0);
+              rh[i] = h;
+              rl[i] = l;
+            }
+          }
         }
-      }
     }
     __syncthreads();
   }
-  // block partial of X^T X: combine the 4 waves in order through LDS
-  __shared__ double red[4][GP][GP];
-#pragma unroll
-  for (int I = 0; I < 3; ++I)
-#pragma unroll
-    for (int J = 0; J < 3; ++J)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) red[wave][16 * I + 4 * q + kg][16 * J + col] = acc[I][J][q];
-  __syncthreads();
   for (int i = threadIdx.x; i < GP * GP; i += blockDim.x) {
-    const int r = i / GP, c = i % GP;
-    double h = red[0][r][c], l = 0.0;
-    for (int w = 1; w < 4; ++w) dd_add_b(h, l, red[w][r][c], 0.0);
-    part[((int64_t)blockIdx.x * GP * GP + i) * 2] = h;
-    part[((int64_t)blockIdx.x * GP * GP + i) * 2 + 1] = l;
+    part[((int64_t)blockIdx.x * GP * GP + i) * 2] = rh[i];
+    part[((int64_t)blockIdx.x * GP * GP + i) * 2 + 1] = rl[i];
   }
 }
 
-// Sum the per-block X^T X in block order and form Gm[k][l] (complex):
+// Sum the per-block X^T X, one wave per element: lane j adds blocks j,
+// j + 64, ... in order (double-double), then a fixed butterfly over the
+// lanes (symmetric in its operands: every lane ends with the same sum).
+__global__ __launch_bounds__(64) void gram_sum_kernel(const double* __restrict__ part, int nblocks,
+                                                      double* __restrict__ xtx) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  double h = 0.0, l = 0.0;
+  for (int b = lane; b < nblocks; b += 64)
+    dd_add_b(h, l, part[((int64_t)b * GP * GP + i) * 2], part[((int64_t)b * GP * GP + i) * 2 + 1]);
+  for (int off = 32; off > 0; off >>= 1) {
+    const double oh = __shfl_xor(h, off), ol = __shfl_xor(l, off);
+    dd_add_b(h, l, oh, ol);
+  }
+  if (lane == 0) xtx[i] = h + l;
+}
+
+// Gm[k][l] (complex) from X^T X:
 //   Re = XtX[k][l] + XtX[K+k][K+l],  Im = XtX[k][K+l] - XtX[K+k][l].
-__global__ void gram_final_kernel(const double* __restrict__ part, int nblocks, int K,
-                                  double* __restrict__ gram) {
-  __shared__ double xtx[GP * GP];
-  for (int i = threadIdx.x; i < GP * GP; i += blockDim.x) {
-    double h = 0.0, l = 0.0;
-    for (int b = 0; b < nblocks; ++b)
-      dd_add_b(h, l, part[((int64_t)b * GP * GP + i) * 2], part[((int64_t)b * GP * GP + i) * 2 + 1]);
-    xtx[i] = h + l;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
-    const int k = i / K, l = i % K;
-    gram[2 * i] = xtx[k * GP + l] + xtx[(K + k) * GP + K + l];
-    gram[2 * i + 1] = xtx[k * GP + K + l] - xtx[(K + k) * GP + l];
-  }
+__global__ void gram_final_kernel(const double* __restrict__ xtx, int K, double* __restrict__ gram) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K * K) return;
+  const int k = i / K, l = i % K;
+  gram[2 * i] = xtx[k * GP + l] + xtx[(K + k) * GP + K + l];
+  gram[2 * i + 1] = xtx[k * GP + K + l] - xtx[(K + k) * GP + l];
 }
 
 // Per-start sum of the row-block partials in two fixed-order stages.  Stage
@@ -485,12 +517,15 @@ hipError_t launch_freeze(int fmt, const double* planes, int64_t stride, int64_t 
 
 hipError_t launch_gram(const double* planes, int64_t stride, int64_t base, int64_t n,
                        const double* tbl, const int* itbl, int K, int gen, int nblocks, double* part,
-                       double* gram, hipStream_t st) {
+                       double* xtx, double* gram, hipStream_t st) {
   hipLaunchKernelGGL(gram_kernel, dim3(nblocks), dim3(256), 0, st, planes, stride, base, n, tbl,
                      itbl, K, gen, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_final_kernel, dim3(1), dim3(1024), 0, st, part, nblocks, K, gram);
+  hipLaunchKernelGGL(gram_sum_kernel, dim3(GP * GP), dim3(64), 0, st, part, nblocks, xtx);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_final_kernel, dim3((K * K + 255) / 256), dim3(256), 0, st, xtx, K, gram);
   return hipGetLastError();
 }
 

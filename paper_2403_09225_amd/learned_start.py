@@ -452,7 +452,39 @@ class ToyStudy:
                 summary[f"mean_seconds_{name}_strategy"] = float(np.mean([r[f"{name}_seconds"] for r in rows]))
         if "blind_success" in rows[0]:
             summary["proposal_vs_blind"] = paired_comparison(rows, "proposal", "blind")
+        # 95% intervals: Wilson for the success rates (the random rate pools
+        # every random start), mean +- 1.96 standard errors for the costs
+        n = len(rows)
+        summary["ci95"] = {
+            "random_start_success_rate": wilson_interval(
+                round(summary["random_start_success_rate"] * n * n_random), n * n_random),
+            "mean_iterations_random_strategy": mean_interval([r["random_iterations"] for r in rows])}
+        for name in ("proposal", "blind"):
+            if f"{name}_success" in rows[0]:
+                summary["ci95"][f"{name}_success_rate"] = wilson_interval(
+                    sum(r[f"{name}_success"] for r in rows), n)
+                summary["ci95"][f"mean_iterations_{name}_strategy"] = mean_interval(
+                    [r[f"{name}_iterations"] for r in rows])
         return summary, rows
+
+
+def wilson_interval(k, n, z=1.959963984540054):
+    """Wilson score interval for a binomial proportion k / n."""
+    if n == 0:
+        return [0.0, 1.0]
+    p = k / n
+    den = 1.0 + z * z / n
+    c = (p + z * z / (2 * n)) / den
+    h = z * math.sqrt(p * (1 - p) / n + z * z / (4 * n * n)) / den
+    return [max(0.0, c - h), min(1.0, c + h)]
+
+
+def mean_interval(x, z=1.959963984540054):
+    """Mean +- z standard errors."""
+    x = np.asarray(x, dtype=np.float64)
+    m = float(np.mean(x))
+    se = float(np.std(x, ddof=1) / math.sqrt(len(x))) if len(x) > 1 else float("inf")
+    return [m - z * se, m + z * se]
 
 
 def sign_test(n_a, n_b):

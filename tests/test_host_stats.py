@@ -28,3 +28,27 @@ def test_paired_comparison_counts():
     assert r["sign_test_p"] == pytest.approx(1.0)
     assert r["mean_iteration_difference"] == pytest.approx((-2 - 40 - 29 + 51 + 0) / 5)
     assert 0.0 < r["wilcoxon_p"] <= 1.0
+
+
+def test_wilson_interval_against_closed_form_cases():
+    """Known values: k = 0 gives [0, z^2 / (n + z^2)]; symmetric about 1/2
+    for k = n / 2; statsmodels-style reference for 12 of 40."""
+    from paper_2403_09225_amd.learned_start import wilson_interval
+    z = 1.959963984540054
+    lo, hi = wilson_interval(0, 20)
+    assert lo == 0.0 and hi == pytest.approx(z * z / (20 + z * z), rel=1e-12)
+    lo, hi = wilson_interval(25, 50)
+    assert lo + hi == pytest.approx(1.0, rel=1e-12)
+    # 12 / 40: centre (p + z^2/2n) / (1 + z^2/n), half-width as defined by Wilson (1927)
+    p, n = 0.3, 40
+    c = (p + z * z / (2 * n)) / (1 + z * z / n)
+    h = z / (1 + z * z / n) * (p * (1 - p) / n + z * z / (4 * n * n)) ** 0.5
+    assert wilson_interval(12, 40) == pytest.approx([c - h, c + h], rel=1e-12)
+    assert wilson_interval(12, 40) == pytest.approx([0.1806, 0.4543], abs=2e-4)
+
+
+def test_mean_interval():
+    from paper_2403_09225_amd.learned_start import mean_interval
+    x = [1.0, 2.0, 3.0, 4.0]
+    m, se = 2.5, (5.0 / 3.0) ** 0.5 / 2.0
+    assert mean_interval(x) == pytest.approx([m - 1.959963984540054 * se, m + 1.959963984540054 * se])
