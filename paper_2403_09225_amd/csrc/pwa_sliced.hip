@@ -95,6 +95,16 @@ __global__ void coupling_slices_kernel(const double* __restrict__ C, int K, int 
 // format's.  An exactly zero Z, which only vanishing couplings or
 // amplitudes give, is not supported.
 //
+// Packed tail.  When at most 8 of the tail's 16 columns are real (2K - 32
+// N32 <= 8, e.g. K = 20), the tail step's upper k-groups carry the next
+// slice instead of zeros, so one 16x16x16 MFMA forms two slice products:
+// the tail of coupling slice s is staged as [c_s | c_(s-1)] (rows of the
+// real columns; zeros under c_0) and the amplitude tails as [q0 | q1] and
+// [q2 | q3] (and [q0 | 0], [q2 | 0]); then
+//   L0 += [q0|0].c0, L1 += [q0|q1].[c1|c0], L2 += [q0|q1].[c2|c1] + [q2|0].c0,
+//   L3 += [q0|q1].[c3|c2] + [q2|q3].[c1|c0]:
+// six tail MFMAs per part instead of ten.
+//
 // MFMA layouts (checked on gfx950): A lane l = row l % 16, k-group l / 16;
 // B lane l = k-group l / 16, column l % 16; result lane l = column l % 16,
 // rows 4 (l / 16) + r.  The chunk's coupling slices sit in LDS in operand
@@ -144,8 +154,9 @@ __device__ __forceinline__ void slice_products(const V* q, const V* cr, const V*
   L[7] = mma_h(q[0], ci[3], L[7]);
 }
 
-template <int N32, int N16>
+template <int N32, int N16, bool PACK>
 __global__ __launch_bounds__(256) void sliced_kernel(BatchArgs a, int nchunk) {
+  static_assert(!PACK || N16 == 1, "the packed tail needs a tail step");
   constexpr int CHB = kSlicedCHB;
   constexpr int NT = CHB / 16;
   constexpr int KP = 32 * N32 + 16 * N16;
@@ -171,15 +182,26 @@ __global__ __launch_bounds__(256) void sliced_kernel(BatchArgs a, int nchunk) {
       uint2 v = {0u, 0u};
       if (b0 + c < B) v = *(const uint2*)(src + ((int64_t)sp * B + b0 + c) * KP + k0);
       const int t = c >> 4, cl = c & 15;
-      int off;
+      _Float16* blk = sC + (t * kSlices * 2 + sp) * TSP;
       if (k0 < 32 * N32) {   // 16x16x32 step k0 / 32: lane 16 kg + col holds k = 8 kg .. 8 kg + 7
         const int kg = (k0 & 31) >> 3;
-        off = (k0 >> 5) * 512 + (kg * 16 + cl) * 8 + (k0 & 7);
+        *(uint2*)(blk + (k0 >> 5) * 512 + (kg * 16 + cl) * 8 + (k0 & 7)) = v;
       } else {               // 16x16x16 tail: lane 16 kg + col holds k = 4 kg .. 4 kg + 3
         const int kg = (k0 - 32 * N32) >> 2;
-        off = N32 * 512 + (kg * 16 + cl) * 4;
+        if constexpr (PACK) {
+          // [c_s | c_(s-1)]: the real rows (k-groups 0, 1) of slice s go to
+          // its own block and to the upper k-groups of slice s + 1's block
+          const int sl = sp >> 1;
+          if (kg < 2) {
+            *(uint2*)(blk + N32 * 512 + (kg * 16 + cl) * 4) = v;
+            if (sl + 1 < kSlices) *(uint2*)(blk + 2 * TSP + N32 * 512 + ((kg + 2) * 16 + cl) * 4) = v;
+          } else if (sl == 0) {
+            *(uint2*)(blk + N32 * 512 + (kg * 16 + cl) * 4) = v;   // zero padding
+          }
+        } else {
+          *(uint2*)(blk + N32 * 512 + (kg * 16 + cl) * 4) = v;
+        }
       }
-      *(uint2*)(sC + (t * kSlices * 2 + sp) * TSP + off) = v;
     }
   }
   __syncthreads();
@@ -201,13 +223,24 @@ __global__ __launch_bounds__(256) void sliced_kernel(BatchArgs a, int nchunk) {
     // operands of rows r0 .. r0 + 15: lane = row l % 16, k-group l / 16
     const int64_t row = min(r0 + col, a.n - 1);
     h8_t q8[N32 > 0 ? N32 : 1][kSlices];
-    h4_t q4[kSlices];
+    h4_t q4[kSlices];   // tail operands; packed: [q0|0], [q0|q1], [q2|0], [q2|q3]
 #pragma unroll
     for (int s = 0; s < kSlices; ++s) {
       const _Float16* ar = A0 + s * plane + row * KP;
 #pragma unroll
       for (int j = 0; j < N32; ++j) q8[j][s] = *(const h8_t*)(ar + 32 * j + 8 * kg);
-      if constexpr (N16 > 0) q4[s] = *(const h4_t*)(ar + 32 * N32 + 4 * kg);
+      if constexpr (N16 > 0 && !PACK) q4[s] = *(const h4_t*)(ar + 32 * N32 + 4 * kg);
+    }
+    if constexpr (PACK) {
+      const int kt = 32 * N32 + 4 * (kg & 1);   // real tail columns only
+      const int up = kg >> 1;                   // upper k-groups: the next slice
+      const h4_t p01 = *(const h4_t*)(A0 + (0 + up) * plane + row * KP + kt);
+      const h4_t p23 = *(const h4_t*)(A0 + (2 + up) * plane + row * KP + kt);
+      const h4_t z = {0, 0, 0, 0};
+      q4[0] = up ? z : p01;
+      q4[1] = p01;
+      q4[2] = up ? z : p23;
+      q4[3] = p23;
     }
     bool valid[4];
 #pragma unroll
@@ -235,7 +268,23 @@ __global__ __launch_bounds__(256) void sliced_kernel(BatchArgs a, int nchunk) {
           cr[s] = *(const h4_t*)(cb + (2 * s) * TSP + N32 * 512 + lane * 4);
           ci[s] = *(const h4_t*)(cb + (2 * s + 1) * TSP + N32 * 512 + lane * 4);
         }
-        slice_products(q4, cr, ci, L);
+        if constexpr (PACK) {
+          // q4 = [q0|0], [q0|q1], [q2|0], [q2|q3]; c = c0, [c1|c0], [c2|c1], [c3|c2]
+          L[6] = mma_h(q4[3], cr[1], L[6]);
+          L[7] = mma_h(q4[3], ci[1], L[7]);
+          L[4] = mma_h(q4[2], cr[0], L[4]);
+          L[5] = mma_h(q4[2], ci[0], L[5]);
+          L[2] = mma_h(q4[1], cr[1], L[2]);
+          L[3] = mma_h(q4[1], ci[1], L[3]);
+          L[0] = mma_h(q4[0], cr[0], L[0]);
+          L[1] = mma_h(q4[0], ci[0], L[1]);
+          L[6] = mma_h(q4[1], cr[3], L[6]);
+          L[7] = mma_h(q4[1], ci[3], L[7]);
+          L[4] = mma_h(q4[1], cr[2], L[4]);
+          L[5] = mma_h(q4[1], ci[2], L[5]);
+        } else {
+          slice_products(q4, cr, ci, L);
+        }
       }
       // epilogue: Z per event in FP64, |Z|^2 into the running product
       double prod = pm[t];
@@ -300,10 +349,18 @@ hipError_t launch_sliced(const BatchArgs& a, int row_blocks, const double* C, in
   if (nchunk > 1 && row_blocks % 8 != 0) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(row_blocks * nchunk));
   const size_t lds = (size_t)kSlices * 2 * kSlicedCHB * a.KP * sizeof(_Float16);
+  // packed tail: at most 8 real columns in the 16-wide tail step
+  const bool pack = (a.KP % 32 == 16) && (2 * K - (a.KP / 32) * 32 <= 8);
   switch (a.KP) {
-    case 16: hipLaunchKernelGGL((sliced_kernel<0, 1>), grid, dim3(256), lds, st, a, nchunk); break;
-    case 32: hipLaunchKernelGGL((sliced_kernel<1, 0>), grid, dim3(256), lds, st, a, nchunk); break;
-    case 48: hipLaunchKernelGGL((sliced_kernel<1, 1>), grid, dim3(256), lds, st, a, nchunk); break;
+    case 16:
+      if (pack) hipLaunchKernelGGL((sliced_kernel<0, 1, true>), grid, dim3(256), lds, st, a, nchunk);
+      else hipLaunchKernelGGL((sliced_kernel<0, 1, false>), grid, dim3(256), lds, st, a, nchunk);
+      break;
+    case 32: hipLaunchKernelGGL((sliced_kernel<1, 0, false>), grid, dim3(256), lds, st, a, nchunk); break;
+    case 48:
+      if (pack) hipLaunchKernelGGL((sliced_kernel<1, 1, true>), grid, dim3(256), lds, st, a, nchunk);
+      else hipLaunchKernelGGL((sliced_kernel<1, 1, false>), grid, dim3(256), lds, st, a, nchunk);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -56,7 +56,7 @@ def test_gram_matches_oracle(K):
 
 
 @pytest.mark.parametrize("K,nd,B", [(5, 3001, 7), (20, 4001, 256), (12, 777, 65), (8, 1000, 1),
-                                    (24, 2999, 130)])
+                                    (24, 2999, 130), (3, 1500, 40), (18, 2500, 70)])
 @pytest.mark.parametrize("fmt", ["f64", "f32", "f16s"])
 def test_batched_nll_accurate_formats(K, nd, B, fmt):
     say(f"[batched] K={K} nd={nd} B={B} {fmt}")
