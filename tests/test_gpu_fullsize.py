@@ -1,7 +1,8 @@
 """Full-size checks on the GPU-scale workload (K = 12 over the three channels,
 1M data-like events, 5M uniform MC events) in the launch configuration the
-benchmark times: the NLL against the oracle over all 6M events, and the
-gradient and H v through properties that hold at any size (phase and scale
+benchmark times: the NLL, the gradient and H v against the oracle over all
+6M events (the oracle in worker processes over event shards, combined by
+eq. (4)-(7)), and properties that hold at any size (phase and scale
 invariance identities, central differences of the GPU NLL, the shard
 identity of eq. (4)-(7), bitwise repeatability)."""
 
@@ -50,6 +51,52 @@ def test_fullsize_nll_against_oracle(k12_hvp):
         assert abs(float(lik.nll(th)) - ref) <= 1e-5 * abs(ref)
     finally:
         lik.set_precision("f64")
+
+
+def test_fullsize_grad_hvp_against_oracle(k12_hvp):
+    """Element-wise over all 6M events: gradient within 1e-10 of S_p and H v
+    within 1e-10 of SH_p (the same yardsticks and bounds as the small-size
+    parity tests), at a point off the minimum.  The oracle runs in 16
+    spawned processes over contiguous shards; its partials combine by
+    eq. (4)-(7) and the absolute sums behind S and SH add over shards."""
+    import multiprocessing as mp
+    import os
+    from tests.oracle_workers import shard
+    W, data, mc, lik = k12_hvp
+    rng = synth.rng_for("k12_hvp", synth.workloads.STREAM_TEST)
+    th = W.theta_true + rng.normal(scale=np.tile([0.02, 0.02, 0.002, 0.002], W.n_res))
+    v = rng.normal(size=48)
+    hv, f, g = lik.hvp(th, v)
+    hv, g = _np(hv), _np(g)
+    n = 16
+    nd, nm = len(data[0]), len(mc[0])
+    bd = [nd * i // n for i in range(n + 1)]
+    bm = [nm * i // n for i in range(n + 1)]
+    jobs = [((data[0][bd[i]:bd[i + 1]], data[1][bd[i]:bd[i + 1]]),
+             (mc[0][bm[i]:bm[i + 1]], mc[1][bm[i]:bm[i + 1]]), W, th, v) for i in range(n)]
+    say(f"[fullsize] grad and H v vs oracle over 6M events ({n} worker processes)")
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(n) as pool:
+            res = pool.map(shard, jobs)
+    finally:
+        for k, val in env.items():
+            if val is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = val
+    ref = oracle.combine([r[0] for r in res], v=v)
+    hF, gF, hG, gG = (np.sum([r[1][j] for r in res], axis=0) for j in range(4))
+    G = sum(r[1][4] for r in res)
+    S = gF + nd / G * gG
+    SH = hF + nd / G * hG + 2.0 * nd / (G * G) * gG * np.sum(np.abs(v) * gG)
+    say(f"  nll {float(f):.10f} vs {ref['nll']:.10f}; max |dg|/S {np.max(np.abs(g - ref['grad']) / S):.3g}, "
+        f"max |dHv|/SH {np.max(np.abs(hv - ref['hv']) / SH):.3g}")
+    assert abs(float(f) - ref["nll"]) <= 1e-10 * abs(ref["nll"])
+    assert np.all(np.abs(g - ref["grad"]) <= 1e-10 * S)
+    assert np.all(np.abs(hv - ref["hv"]) <= 1e-10 * SH)
 
 
 def test_fullsize_invariance_identities(k12_hvp):
