@@ -7,6 +7,13 @@ and 20M MC events, FP64 and FP32 event streams.
 * over all 24M events: the GPU FP64 NLL's central difference (Richardson,
   h = 1e-6 and 5e-7) along a random direction equals g . d, and the central
   difference of GPU gradients equals H d;
+* over all 24M events, gradient and H v element by element against the
+  oracle (16 worker processes over event shards, eq. (4)-(7) combine): FP64
+  stream to 1e-10 of the absolute-sum scales; FP32 stream gradient to 3e-5
+  of S and H v to 3e-4 of SH (the stream's s, u, g are rounded at 2^-24 and
+  the H v terms carry up to three powers of w = 1/D, whose derivatives
+  amplify that rounding near the narrow resonances; measured 1.3e-4, as
+  the 1e-4 level of the FP32 Hessian entries);
 * the FP32 stream (FP64 reductions) tracks the FP64 stream: NLL to 1e-5
   relative, gradient and H v to 1e-3 of their largest component;
 * the autograd wrapper's double backward returns pwa_hvp's H v;
@@ -59,6 +66,50 @@ def test_k30_subsample_against_oracle(k30_diff):
     assert abs(float(f_g) - f) <= 1e-10 * abs(f)
     assert_close("grad", _np(g_g), g, S, 1e-10)
     assert_close("hvp", _np(hv_g), hv, SH, 1e-10)
+
+
+def test_k30_fullsize_against_oracle(k30_diff):
+    import multiprocessing as mp
+    import os
+    from tests.oracle_workers import shard
+    W, data, mc, lik = k30_diff
+    th = W.theta_true
+    v = synth.rng_for("k30_diff", 9).normal(size=W.n_par)
+    n = 16
+    nd, nm = len(data[0]), len(mc[0])
+    bd = [nd * i // n for i in range(n + 1)]
+    bm = [nm * i // n for i in range(n + 1)]
+    jobs = [((data[0][bd[i]:bd[i + 1]], data[1][bd[i]:bd[i + 1]]),
+             (mc[0][bm[i]:bm[i + 1]], mc[1][bm[i]:bm[i + 1]]), W, th, v) for i in range(n)]
+    say(f"[k30_diff] grad and H v vs oracle over {nd + nm} events ({n} worker processes)")
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(n) as pool:
+            res = pool.map(shard, jobs)
+    finally:
+        for k, val in env.items():
+            if val is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = val
+    ref = oracle.combine([r[0] for r in res], v=v)
+    hF, gF, hG, gG = (np.sum([r[1][j] for r in res], axis=0) for j in range(4))
+    G = sum(r[1][4] for r in res)
+    S = gF + nd / G * gG
+    SH = hF + nd / G * hG + 2.0 * nd / (G * G) * gG * np.sum(np.abs(v) * gG)
+    for prec, tol_f, tol, tol_h in (("f64", 1e-10, 1e-10, 1e-10), ("f32", 1e-5, 3e-5, 3e-4)):
+        lik.set_precision(prec)
+        try:
+            hv, f, g = [_np(x) for x in lik.hvp(th, v)]
+        finally:
+            lik.set_precision("f64")
+        say(f"  {prec}: max |dg|/S {np.max(np.abs(g - ref['grad']) / S):.3g}, "
+            f"max |dHv|/SH {np.max(np.abs(hv - ref['hv']) / SH):.3g}")
+        assert abs(float(f) - ref["nll"]) <= tol_f * abs(ref["nll"])
+        assert np.all(np.abs(g - ref["grad"]) <= tol * S)
+        assert np.all(np.abs(hv - ref["hv"]) <= tol_h * SH)
 
 
 def test_k30_central_differences(k30_diff):
