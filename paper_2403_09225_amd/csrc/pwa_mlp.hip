@@ -109,6 +109,11 @@ struct GemmArgs {
   int m_valid;         // FWD_OUT: rows stored
 };
 
+// gfx950's 16x16x32 bf16 MFMA over the inner dimension (A and B lanes: row
+// or column l % 16, 8 consecutive k at 8 (l / 16)), one 16x16x16 step for a
+// 16-wide tail (K is padded to a multiple of 16).
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
 template <int MODE>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -119,20 +124,34 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
   const uint16_t* pb[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    pa[i] = g.A + (int64_t)min(m0 + 16 * i + r, g.M - 1) * g.lda + 4 * kg;
-    pb[i] = g.B + (int64_t)min(n0 + 16 * i + r, g.N - 1) * g.ldb + 4 * kg;
+    pa[i] = g.A + (int64_t)min(m0 + 16 * i + r, g.M - 1) * g.lda;
+    pb[i] = g.B + (int64_t)min(n0 + 16 * i + r, g.N - 1) * g.ldb;
   }
   f4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (f4_t){0.f, 0.f, 0.f, 0.f};
-  for (int k = 0; k < g.K; k += 16) {
+  int k = 0;
+  for (; k + 32 <= g.K; k += 32) {
+    bf8_t a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      __builtin_memcpy(&a[i], pa[i] + k + 8 * kg, sizeof(bf8_t));
+      __builtin_memcpy(&b[i], pb[i] + k + 8 * kg, sizeof(bf8_t));
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+  if (k < g.K) {
     s4_t a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      a[i] = *(const s4_t*)(pa[i] + k);
-      b[i] = *(const s4_t*)(pb[i] + k);
+      a[i] = *(const s4_t*)(pa[i] + k + 4 * kg);
+      b[i] = *(const s4_t*)(pb[i] + k + 4 * kg);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
