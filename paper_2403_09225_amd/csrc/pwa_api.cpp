@@ -112,12 +112,16 @@ Layout layout_of(const pwa_ctx* c, int64_t n_data, int64_t n_mc) {
 
 bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 
-// Automatic launch shape.  Layout 2 (a block of G waves shares each batch of
-// 64 events, wave g owns R resonances) keeps the resonance table and plane
-// pointers in scalar registers; the choice covers K with the fewest padded
-// resonance slots at R <= 3 (FP64 moment accumulators: 18 R per lane), and
-// 8 waves of 4 resonances (one block per CU) for 24 < K <= 32.  Layout 1
-// (T lanes of a wave share an event) serves K > 32.
+// Automatic launch shape, for every pass (NLL, NLL + grad, H v).  Layout 2
+// (a block of G waves shares each batch of 64 events, wave g owns R
+// resonances, the event planes staged into LDS) keeps the resonance table
+// and plane pointers in scalar registers; the choice covers K with the
+// fewest padded resonance slots at R <= 3 (FP64 moment accumulators: 18 R
+// per lane), and 8 waves of 4 resonances (one block per CU) for
+// 24 < K <= 32.  Layout 1 (T lanes of a wave share an event) serves K > 32.
+// For the NLL alone layout 2 also beats one lane per event with all
+// resonances (layout 1, T = 1): 157 against 191 us at K = 12, 222 against
+// 426 us at K = 30 (6M events, FP64).
 void auto_shape(int K, int& L, int& T, int& R) {
   L = 2;
   if (K <= 2) { T = 1; R = 2; return; }
@@ -130,20 +134,6 @@ void auto_shape(int K, int& L, int& T, int& R) {
   if (K <= 32) { T = 8; R = 4; return; }
   L = 1;
   T = 32; R = 2;
-}
-
-// The NLL-only pass keeps no moment accumulators: one lane per event with
-// all resonances (layout 1, T = 1) avoids any exchange between lanes.
-bool auto_nll_shape(int K, int& L, int& T, int& R) {
-  const int rs[] = {8, 12, 16, 24, 32};
-  for (int r : rs)
-    if (K <= r) {
-      L = 1;
-      T = 1;
-      R = r;
-      return true;
-    }
-  return false;
 }
 
 // General physics path (layout 3): G waves of 2 resonances.
@@ -164,7 +154,6 @@ void shape_of(const pwa_ctx* c, int mode, int& L, int& T, int& R) {
     }
     return;
   }
-  if (c->shape_L == 0 && mode == MODE_NLL && auto_nll_shape(c->K, L, T, R)) return;
   if (c->shape_L > 0) {
     L = c->shape_L;
     T = c->shape_T;
