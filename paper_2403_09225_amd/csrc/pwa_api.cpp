@@ -117,8 +117,11 @@ bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 // resonances, the event planes staged into LDS) keeps the resonance table
 // and plane pointers in scalar registers; the choice covers K with the
 // fewest padded resonance slots at R <= 3 (FP64 moment accumulators: 18 R
-// per lane), and 8 waves of 4 resonances (one block per CU) for
-// 24 < K <= 32.  Layout 1 (T lanes of a wave share an event) serves K > 32.
+// per lane), and 8 waves of 3 or 4 resonances (512-thread blocks, at most 2
+// waves per SIMD) for 16 < K <= 32.  A 12-wave block would hold 3 waves per
+// SIMD, which caps a wave at 168 VGPRs: the FP64 H v build of 12 x 2 then
+// spills and runs 4x slower than 8 x 3 (2.47 against 0.59 ms at K = 20,
+// 6M events).  Layout 1 (T lanes of a wave share an event) serves K > 32.
 // For the NLL alone layout 2 also beats one lane per event with all
 // resonances (layout 1, T = 1): 157 against 191 us at K = 12, 222 against
 // 426 us at K = 30 (6M events, FP64).
@@ -130,7 +133,7 @@ void auto_shape(int K, int& L, int& T, int& R) {
   if (K <= 8) { T = 4; R = 2; return; }
   if (K <= 12) { T = 4; R = 3; return; }
   if (K <= 16) { T = 8; R = 2; return; }
-  if (K <= 24) { T = 12; R = 2; return; }
+  if (K <= 24) { T = 8; R = 3; return; }
   if (K <= 32) { T = 8; R = 4; return; }
   L = 1;
   T = 32; R = 2;
