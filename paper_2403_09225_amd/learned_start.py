@@ -25,6 +25,7 @@ onto [-1, 1].
 import ctypes
 import math
 import os
+import threading
 import time
 
 import numpy as np
@@ -306,7 +307,7 @@ def fit(lik, start, xtol=1e-6, maxiter=100, time_cap_s=5.0):
 class ToyStudy:
     """Toys of one resonance layout with a shared MC sample."""
 
-    def __init__(self, channel, spin, n_mc, prior=None, seed=0, device="cuda"):
+    def __init__(self, channel, spin, n_mc, prior=None, seed=0, device="cuda", mc=None):
         self.channel, self.spin = list(channel), list(spin)
         self.prior = prior if prior is not None else Prior.wide(channel)
         self.coder = StartCoder(channel, spin, self.prior)
@@ -314,8 +315,10 @@ class ToyStudy:
         self.gen.manual_seed(seed)
         self.rng = np.random.Generator(np.random.PCG64(seed))
         self.toys = ToyGenerator(channel, spin, batch=1 << 19, scan=1 << 18, device=device)
-        from .toys import uniform_dalitz
-        self.mc = uniform_dalitz(n_mc, self.gen, device=device)
+        if mc is None:
+            from .toys import uniform_dalitz
+            mc = uniform_dalitz(n_mc, self.gen, device=device)
+        self.mc = mc
         self.device = device
 
     def toy(self, n_events):
@@ -388,6 +391,12 @@ class ToyStudy:
         return [self.coder.decode(r) for r in y]
 
     def evaluate(self, net, n_toys, n_events, n_random, tol=0.01, log_every=0, blind=None):
+        """(summary, rows) of evaluate_rows on n_toys toys."""
+        rows = self.evaluate_rows(net, n_toys, n_events, n_random, tol, log_every, blind)
+        return summarize(rows, n_events, n_random, tol), rows
+
+    def evaluate_rows(self, net, n_toys, n_events, n_random, tol=0.01, log_every=0, blind=None,
+                      net_lock=None):
         """Proposal-started fits against random multi-start on held-out toys.
 
         Per toy, NLL_min is the lowest NLL of all its fits (from the truth,
@@ -398,13 +407,19 @@ class ToyStudy:
         full); a single-start strategy (the proposal, or the blind start
         `blind` -- one fixed start that ignores the data, e.g. the decoded
         mean training label) costs its own fit plus, when that fails, the
-        random strategy's expected cost."""
+        random strategy's expected cost.  One row per toy.  With net_lock
+        (workers sharing one network), the proposal is taken under it."""
         rows = []
         t0 = time.time()
         for i in range(n_toys):
             th, ev = self.toy(n_events)
             lik = self.likelihood(ev)
-            start = self.propose(net, self.features(ev, n_events))[0]
+            feats = self.features(ev, n_events)
+            if net_lock is None:
+                start = self.propose(net, feats)[0]
+            else:
+                with net_lock:   # the network's workspace is shared
+                    start = self.propose(net, feats)[0]
             fits = {"truth": fit(lik, th), "proposal": fit(lik, start)}
             if blind is not None:
                 fits["blind"] = fit(lik, blind)
@@ -438,34 +453,113 @@ class ToyStudy:
             if log_every and (i + 1) % log_every == 0:
                 print(f"[learned-start] evaluated {i + 1}/{n_toys} toys, {time.time() - t0:.1f} s",
                       flush=True)
-        summary = {
-            "toys": n_toys, "events_per_toy": n_events, "random_starts": n_random, "tol": tol,
-            "random_start_success_rate": float(np.mean([r["random_success_fraction"] for r in rows])),
-            "random_found_fraction": float(np.mean([r["random_found"] for r in rows])),
-            "mean_iterations_random_strategy": float(np.mean([r["random_iterations"] for r in rows])),
-            "mean_seconds_random_strategy": float(np.mean([r["random_seconds"] for r in rows])),
-        }
-        for name in ("proposal", "blind"):
-            if f"{name}_success" in rows[0]:
-                summary[f"{name}_success_rate"] = float(np.mean([r[f"{name}_success"] for r in rows]))
-                summary[f"mean_iterations_{name}_strategy"] = float(np.mean([r[f"{name}_iterations"] for r in rows]))
-                summary[f"mean_seconds_{name}_strategy"] = float(np.mean([r[f"{name}_seconds"] for r in rows]))
-        if "blind_success" in rows[0]:
-            summary["proposal_vs_blind"] = paired_comparison(rows, "proposal", "blind")
-        # 95% intervals: Wilson for the success rates (the random rate pools
-        # every random start), mean +- 1.96 standard errors for the costs
-        n = len(rows)
-        summary["ci95"] = {
-            "random_start_success_rate": wilson_interval(
-                round(summary["random_start_success_rate"] * n * n_random), n * n_random),
-            "mean_iterations_random_strategy": mean_interval([r["random_iterations"] for r in rows])}
-        for name in ("proposal", "blind"):
-            if f"{name}_success" in rows[0]:
-                summary["ci95"][f"{name}_success_rate"] = wilson_interval(
-                    sum(r[f"{name}_success"] for r in rows), n)
-                summary["ci95"][f"mean_iterations_{name}_strategy"] = mean_interval(
-                    [r[f"{name}_iterations"] for r in rows])
-        return summary, rows
+        return rows
+
+
+def summarize(rows, n_events, n_random, tol):
+    """Success rates, expected costs, the paired proposal-vs-blind comparison
+    and 95% intervals over the evaluation rows."""
+    n_toys = len(rows)
+    summary = {
+        "toys": n_toys, "events_per_toy": n_events, "random_starts": n_random, "tol": tol,
+        "random_start_success_rate": float(np.mean([r["random_success_fraction"] for r in rows])),
+        "random_found_fraction": float(np.mean([r["random_found"] for r in rows])),
+        "mean_iterations_random_strategy": float(np.mean([r["random_iterations"] for r in rows])),
+        "mean_seconds_random_strategy": float(np.mean([r["random_seconds"] for r in rows])),
+    }
+    for name in ("proposal", "blind"):
+        if f"{name}_success" in rows[0]:
+            summary[f"{name}_success_rate"] = float(np.mean([r[f"{name}_success"] for r in rows]))
+            summary[f"mean_iterations_{name}_strategy"] = float(np.mean([r[f"{name}_iterations"] for r in rows]))
+            summary[f"mean_seconds_{name}_strategy"] = float(np.mean([r[f"{name}_seconds"] for r in rows]))
+    if "blind_success" in rows[0]:
+        summary["proposal_vs_blind"] = paired_comparison(rows, "proposal", "blind")
+    if "proposal_success" in rows[0]:
+        summary["proposal_vs_random"] = paired_costs(rows, "proposal", "random")
+    # 95% intervals: Wilson for the success rates (the random rate pools
+    # every random start), mean +- 1.96 standard errors for the costs
+    n = len(rows)
+    summary["ci95"] = {
+        "random_start_success_rate": wilson_interval(
+            round(summary["random_start_success_rate"] * n * n_random), n * n_random),
+        "mean_iterations_random_strategy": mean_interval([r["random_iterations"] for r in rows])}
+    for name in ("proposal", "blind"):
+        if f"{name}_success" in rows[0]:
+            summary["ci95"][f"{name}_success_rate"] = wilson_interval(
+                sum(r[f"{name}_success"] for r in rows), n)
+            summary["ci95"][f"mean_iterations_{name}_strategy"] = mean_interval(
+                [r[f"{name}_iterations"] for r in rows])
+    return summary
+
+
+def split_counts(n, parts):
+    """n items over `parts` workers, as even as possible."""
+    return [n // parts + (1 if w < n % parts else 0) for w in range(parts)]
+
+
+def run_workers(n_workers, make_study, work):
+    """work(study, w) for w = 0 .. n_workers-1, each in a host thread of its
+    own with its own HIP stream (default priority) and its own ToyStudy
+    (make_study(w), built on that stream).  The library's calls release the
+    interpreter lock, so the workers' fits -- many small kernels and host
+    round trips each -- overlap on the GPU.  Returns the results in worker
+    order; tensors in them may be used on the caller's stream."""
+    main = torch.cuda.current_stream()
+    main.synchronize()   # inputs shared by the workers (the MC sample) are ready
+    results, errors = [None] * n_workers, []
+
+    def run(w):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                results[w] = work(make_study(w), w)
+            st.synchronize()
+        except BaseException as e:   # re-raised in the caller
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(w,)) for w in range(n_workers)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if errors:
+        raise errors[0]
+    for res in results:
+        for x in (res if isinstance(res, tuple) else ()):
+            if isinstance(x, torch.Tensor) and x.is_cuda:
+                x.record_stream(main)
+    return results
+
+
+def parallel_training_set(channel, spin, prior, mc, n_toys, n_events, n_workers, seed, n_rep=0,
+                          log_every=0):
+    """ToyStudy.training_set over n_workers workers (toy streams seeded
+    seed * 1000 + w), merged with the toy index made unique per worker."""
+    counts = split_counts(n_toys, n_workers)
+    res = run_workers(
+        n_workers,
+        lambda w: ToyStudy(channel, spin, 0, prior=prior, seed=seed * 1000 + w, mc=mc),
+        lambda st, w: st.training_set(counts[w], n_events, log_every=log_every, n_rep=n_rep))
+    off = np.cumsum([0] + counts)
+    x = torch.cat([r[0] for r in res])
+    y = torch.cat([r[1] for r in res])
+    ids = np.concatenate([r[2] + off[w] for w, r in enumerate(res)])
+    return x, y, ids
+
+
+def parallel_evaluate(channel, spin, prior, mc, net, n_toys, n_events, n_random, n_workers, seed,
+                      blind=None, tol=0.01, log_every=0):
+    """ToyStudy.evaluate over n_workers workers (toy streams seeded
+    seed * 1000 + w); (summary, rows)."""
+    counts = split_counts(n_toys, n_workers)
+    lock = threading.Lock()
+    res = run_workers(
+        n_workers,
+        lambda w: ToyStudy(channel, spin, 0, prior=prior, seed=seed * 1000 + w, mc=mc),
+        lambda st, w: st.evaluate_rows(net, counts[w], n_events, n_random, tol, log_every, blind,
+                                       net_lock=lock))
+    rows = [r for part in res for r in part]
+    return summarize(rows, n_events, n_random, tol), rows
 
 
 def wilson_interval(k, n, z=1.959963984540054):
@@ -517,13 +611,31 @@ def paired_comparison(rows, a, b):
             "median_iteration_difference": float(np.median(d)), "wilcoxon_p": p_w}
 
 
+def paired_costs(rows, a, b):
+    """Per-toy difference of the expected Newton iterations and seconds to
+    the global minimum of strategy a minus strategy b (e.g. the proposal
+    strategy against random multi-start), with Wilcoxon signed-rank tests."""
+    out = {"toys": len(rows)}
+    for key in ("iterations", "seconds"):
+        d = np.array([r[f"{a}_{key}"] - r[f"{b}_{key}"] for r in rows], dtype=np.float64)
+        p_w = 1.0
+        if np.any(d != 0):
+            from scipy.stats import wilcoxon
+            p_w = float(wilcoxon(d, zero_method="wilcox", alternative="two-sided").pvalue)
+        out[f"mean_{key}_difference"] = float(np.mean(d))
+        out[f"median_{key}_difference"] = float(np.median(d))
+        out[f"{key}_wilcoxon_p"] = p_w
+    out[f"toys_{a}_cheaper"] = int(sum(r[f"{a}_iterations"] < r[f"{b}_iterations"] for r in rows))
+    return out
+
+
 DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
 
 
 def load_proposal(path=None, device="cuda"):
     """A trained start proposal: (network, prior, blind start, metadata).
     The default is the K = 12 network shipped in data/ (trained by this
-    module's main() on 4500 toy fits; see its metadata)."""
+    module's main() on 18000 toy fits of 50k events; see its metadata)."""
     net, meta = MLP.load(path or os.path.join(DATA, "start_proposal_k12.npz"), device=device)
     K = int(meta["K"])
     ch, _ = resonance_layout(K)
@@ -564,16 +676,36 @@ def main(argv=None):
                     "to this .npz")
     ap.add_argument("--save-set", default="", help="save the training features (one row per "
                     "toy, float16) and labels to this .npz")
+    ap.add_argument("--threads", type=int, default=1, help="host threads (each with its own "
+                    "HIP stream) running toy fits side by side; 1 keeps the single-stream order")
     ap.add_argument("--evaluate-shipped", action="store_true",
                     help="only evaluate the shipped proposal (data/) on --eval fresh toys of "
                     "--eval-events events, seeded by --seed")
+    ap.add_argument("--net", default="", help="with --evaluate-shipped: evaluate this saved "
+                    "network (.npz from --save-net) instead of the shipped one")
     a = ap.parse_args(argv)
+    if a.threads < 1:
+        ap.error("--threads must be at least 1")
+
+    def shared_mc(seed):
+        from .toys import uniform_dalitz
+        g = torch.Generator(device="cuda")
+        g.manual_seed(seed)
+        return uniform_dalitz(a.mc, g)
+
+    def evaluate(ch, sp, prior, net, blind, seed, log_every):
+        if a.threads == 1:
+            ev = ToyStudy(ch, sp, a.mc, prior=prior, seed=seed)
+            return ev.evaluate(net, a.eval, a.eval_events, a.random, log_every=log_every,
+                               blind=blind)
+        return parallel_evaluate(ch, sp, prior, shared_mc(seed), net, a.eval, a.eval_events,
+                                 a.random, a.threads, seed, blind=blind, log_every=log_every)
+
     if a.evaluate_shipped:
-        net, prior, blind, meta = load_proposal()
+        net, prior, blind, meta = load_proposal(a.net or None)
         ch, sp = resonance_layout(int(meta["K"]))
-        ev = ToyStudy(ch, sp, a.mc, prior=prior, seed=a.seed)
-        summary, rows = ev.evaluate(net, a.eval, a.eval_events, a.random,
-                                    log_every=max(1, min(10, a.eval // 10)), blind=blind)
+        summary, rows = evaluate(ch, sp, prior, net, blind, a.seed,
+                                 max(1, min(10, a.eval // (10 * a.threads))))
         print(json.dumps(summary), flush=True)
         if a.out:
             with open(a.out, "w") as f:
@@ -588,8 +720,13 @@ def main(argv=None):
         prior = Prior.wide(ch)
     t0 = time.time()
     study = ToyStudy(ch, sp, a.mc, prior=prior, seed=a.seed)
-    x, y, ids = study.training_set(a.train, a.events, log_every=max(1, min(50, a.train // 10)),
-                                   n_rep=a.rep)
+    if a.threads == 1:
+        x, y, ids = study.training_set(a.train, a.events, log_every=max(1, min(50, a.train // 10)),
+                                       n_rep=a.rep)
+    else:
+        x, y, ids = parallel_training_set(ch, sp, prior, study.mc, a.train, a.events, a.threads,
+                                          a.seed, n_rep=a.rep,
+                                          log_every=max(1, min(200, a.train // (10 * a.threads))))
     t_data = time.time() - t0
     if a.save_set:
         first = np.concatenate([[True], ids[1:] != ids[:-1]])
@@ -627,12 +764,16 @@ def main(argv=None):
                  g_spread=prior.g_spread, c_range=np.asarray(prior.c_range),
                  train_toys=int(len(toys) - n_val), train_events=a.events, mc=a.mc,
                  val_loss_best=min(vh) if vh else np.nan, seed=a.seed)
-    ev = ToyStudy(ch, sp, a.mc, prior=prior, seed=a.seed + 1000)
-    summary, _ = ev.evaluate(net, a.eval, a.eval_events, a.random, log_every=max(1, min(5, a.eval // 10)),
-                             blind=blind)
+    if a.eval > 0:
+        summary, _ = evaluate(ch, sp, prior, net, blind, a.seed + 1000,
+                              max(1, min(5, a.eval // (10 * a.threads))))
+    else:
+        summary = {}
     summary.update({"K": a.K, "m_spread": a.m_spread, "g_spread": a.g_spread, "weight_decay": wd_best, "train_toys": int(len(toys) - n_val), "val_toys": n_val,
                     "train_rows": int(x.shape[0]), "train_events": a.events, "mc": a.mc,
                     "epochs": a.epochs, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
+                    "val_loss_first_epoch": vh[0] if vh else None,
+                    "val_epoch_best": int(np.argmin(vh)) + 1 if vh else None,
                     "val_loss_best": min(vh) if vh else None,
                     "seconds_training_set": round(t_data, 1), "seconds_training": round(t_train, 1)})
     print(json.dumps(summary), flush=True)

@@ -52,3 +52,26 @@ def test_mean_interval():
     x = [1.0, 2.0, 3.0, 4.0]
     m, se = 2.5, (5.0 / 3.0) ** 0.5 / 2.0
     assert mean_interval(x) == pytest.approx([m - 1.959963984540054 * se, m + 1.959963984540054 * se])
+
+
+def test_split_counts_covers_every_item_evenly():
+    from paper_2403_09225_amd.learned_start import split_counts
+    for n, parts in [(0, 3), (7, 1), (10, 3), (96, 8), (5, 8)]:
+        c = split_counts(n, parts)
+        assert len(c) == parts and sum(c) == n and max(c) - min(c) <= 1
+
+
+def test_paired_costs_against_hand_computed_differences():
+    from scipy.stats import wilcoxon
+    from paper_2403_09225_amd.learned_start import paired_costs
+    pi = [10.0, 80.0, 30.0, 200.0, 5.0, 60.0]
+    ri = [50.0, 70.0, 90.0, 210.0, 45.0, 100.0]
+    rows = [{"proposal_iterations": a, "random_iterations": b,
+             "proposal_seconds": a / 100, "random_seconds": b / 100} for a, b in zip(pi, ri)]
+    r = paired_costs(rows, "proposal", "random")
+    d = [a - b for a, b in zip(pi, ri)]
+    assert r["mean_iterations_difference"] == pytest.approx(sum(d) / 6)
+    assert r["median_iterations_difference"] == pytest.approx(-40.0)   # -60, -40, -40, -40, -10, 10
+    assert r["iterations_wilcoxon_p"] == pytest.approx(wilcoxon(d).pvalue)
+    assert r["mean_seconds_difference"] == pytest.approx(sum(d) / 600)
+    assert r["toys_proposal_cheaper"] == 5
