@@ -273,6 +273,66 @@ def k30_bench(steps=20):
     return out
 
 
+def general_bench(reps=20):
+    """The general physics path on the GPU-scale layout (K = 12, 1M data +
+    5M MC events, uniform over phase space and parent orientation, FP64
+    stream): a Flatte f0(980)-like scalar in the (23) channel (Sec. 3's
+    model), a spin-1 parent with two helicity amplitudes per event (eq. (1),
+    mu = +1, -1), and both.  Per-event kernel time of the fused
+    NLL+grad+HVP, NLL+grad and NLL passes, events/s, and the HBM fraction of
+    the stream bytes (planes x 8 B per event, read once per pass)."""
+    import torch
+    import synth
+    from paper_2403_09225_amd import Likelihood
+    ch, sp = synth.resonance_layout(12)
+    nd, nm = 1_000_000, 5_000_000
+    rng = np.random.Generator(np.random.PCG64(11))
+    ev = []
+    for n in (nd, nm):
+        s12, s13 = synth.uniform_phase_space(n, rng)
+        cb, g = synth.uniform_orientation(n, rng)
+        ev.append((s12, s13, cb, g))
+    th0 = synth.draw_theta(ch, sp, np.random.Generator(np.random.PCG64(12)))
+    kf = next(k for k in range(len(ch)) if ch[k] == 2 and sp[k] == 0)
+    ls = [1 if k == kf else 0 for k in range(len(ch))]
+    v = torch.tensor(np.random.Generator(np.random.PCG64(13)).normal(size=4 * len(ch)),
+                     dtype=torch.float64, device="cuda")
+    out = {"workload": f"K=12, {nd} data + {nm} MC events (uniform), FP64 stream; Flatte "
+                       f"resonance {kf} (channel (23), J = 0)"}
+    for name, lshape, ps in (("flatte", ls, 0), ("spin1", None, 1), ("spin1_flatte", ls, 1)):
+        lik = Likelihood(ch, sp, lineshape=lshape, flatte_masses=synth.FLATTE_MASSES,
+                         flatte_ratio=synth.FLATTE_RATIO, parent_spin=ps)
+        if ps == 1:
+            lik.bind_oriented(ev[0], ev[1])
+        else:
+            lik.bind(ev[0][0], ev[0][1], ev[1][0], ev[1][1])
+        th = th0.copy()
+        if lshape:
+            th[4 * kf + 2:4 * kf + 4] = synth.FLATTE_F0
+        th = torch.tensor(th, dtype=torch.float64, device="cuda")
+        fields = lik.stream_fields()
+        rec = {"stream_fields": fields}
+        for mode, fn in (("hvp", lambda: lik.hvp(th, v)), ("grad", lambda: lik.grad(th)),
+                         ("nll", lambda: lik.nll(th))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            lik.set_kernel_timing(True)
+            lik.kernel_time()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            k_ms, k_n = lik.kernel_time()
+            lik.set_kernel_timing(False)
+            us = k_ms / max(k_n, 1) * 1e3
+            rec[mode] = {"kernel_us": round(us, 2), "events_per_s": round((nd + nm) / us * 1e6, 1),
+                         "hbm_frac": round((nd + nm) * fields * 8 / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+        out[name] = rec
+        del lik
+        torch.cuda.empty_cache()
+    return out
+
+
 def entry_point_times(lik, th, v, reps=20):
     """Per-call time of pwa_nll, pwa_grad, pwa_hvp and pwa_hvp_reuse (an HVP
     at the theta of the last pwa_hvp, as inside CG) on the FP64 and FP32
@@ -392,6 +452,8 @@ def main():
     ap.add_argument("--shape", default="", help="layout,groups,res_per_group override (layout 0: lanes per event, 1: waves per block)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-k30", action="store_true", help="skip the K = 30, 24M-event section")
+    ap.add_argument("--no-general", action="store_true",
+                    help="skip the general physics path section (Flatte, spin-1 parent)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -520,7 +582,7 @@ def main():
     if not args.no_fit:
         result["newton_cg_time_to_min"] = fit_compare(lik, W)
         print("[bench] fits done", file=sys.stderr, flush=True)
-    if not args.no_batched or not args.no_k30:
+    if not args.no_batched or not args.no_k30 or not args.no_general:
         del lik
         torch.cuda.empty_cache()
     if not args.no_batched:
@@ -531,6 +593,10 @@ def main():
         result["k30_differentiation"] = k30_bench()
         torch.cuda.empty_cache()
         print("[bench] K = 30 workload done", file=sys.stderr, flush=True)
+    if not args.no_general:
+        result["general_physics_path"] = general_bench()
+        torch.cuda.empty_cache()
+        print("[bench] general physics path done", file=sys.stderr, flush=True)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(W, data, mc)
         result["cpu_all_cores"] = cpu_all_cores(W, data, mc)

@@ -396,12 +396,19 @@ const char* pwa_status_str(int status);
 /* Number of parameters P = 4K of a context (or -1 for null). */
 int32_t pwa_n_par(const pwa_ctx* ctx);
 
+/* Number of per-event planes of the context's parameter-free event stream
+ * (Sec. 2.2: the precomputed per-event factors), or -1 for null.  Each pass
+ * reads every plane once per event: 8 bytes per plane and event on the FP64
+ * stream, 4 on the FP32 one.  Fixed by the model at pwa_create. */
+int32_t pwa_stream_fields(const pwa_ctx* ctx);
+
 /* Launch shape of the NLL/gradient/HVP pass kernels (for tuning; the
  * default is an automatic choice by K).  layout 1: `groups` lanes of one
  * wavefront cooperate on each event; layout 2: `groups` wavefronts of one
  * block cooperate on each batch of 64 events; layout 3: the same for models
  * with a Flatte resonance or a spin-1 parent (the only layout those use;
- * groups in {1, 2, 4, 8}, res_per_group 2, so K <= 16 there).  Each lane
+ * groups in {1, 2, 4, 8} with res_per_group 2, or 4 groups of 3, so
+ * K <= 16 there).  Each lane
  * owns `res_per_group` resonances; groups * res_per_group >= K.  layout 0
  * restores the automatic choice.  PWA_E_INVALID for a shape that is not
  * built or does not fit the model. */

@@ -79,6 +79,7 @@ SIGNATURES = {
     "pwa_device_status": (c_int32, [_P, _P]),
     "pwa_status_str": (ctypes.c_char_p, [c_int32]),
     "pwa_n_par": (c_int32, [_P]),
+    "pwa_stream_fields": (c_int32, [_P]),
     "pwa_set_launch_shape": (c_int32, [_P, c_int32, c_int32, c_int32]),
     "pwa_grid_blocks": (c_int32, [_P]),
     "pwa_set_kernel_timing": (c_int32, [_P, c_int32]),

@@ -137,6 +137,11 @@ class Likelihood:
     def grid_blocks(self):
         return int(self.lib.pwa_grid_blocks(self._h))
 
+    def stream_fields(self):
+        """Per-event planes of the event stream (8 bytes each per event on the
+        FP64 stream, 4 on the FP32 one)."""
+        return int(self.lib.pwa_stream_fields(self._h))
+
     def set_kernel_timing(self, enable=True):
         L.check("pwa_set_kernel_timing", self.lib.pwa_set_kernel_timing(self._h, 1 if enable else 0))
 

@@ -1793,7 +1793,7 @@ static EvalFn wg_fn(int is_f32, int mode, int G, int R) {
 }
 
 // General physics path shapes (waves per block G, resonances per wave R).
-#define PWA_GEN_SHAPES(X) X(1, 2) X(2, 2) X(4, 2) X(8, 2)
+#define PWA_GEN_SHAPES(X) X(1, 2) X(2, 2) X(4, 2) X(8, 2) X(4, 3)
 
 bool gen_shape_built(int G, int R) {
 #define PWA_IS(GG, RR) if (G == GG && R == RR) return true;

@@ -82,6 +82,8 @@ def test_valid_context_host_queries(lib):
     assert code == L.PWA_OK
     try:
         assert lib.pwa_n_par(h) == 48
+        assert lib.pwa_stream_fields(h) == 18   # 3 s, 6 u, 9 g planes
+        assert lib.pwa_stream_fields(None) == -1
         assert lib.pwa_workspace_bytes(h, -1, 10) == 0
         assert lib.pwa_workspace_bytes(h, 10, 0) == 0
         a = lib.pwa_workspace_bytes(h, 1000, 5000)
@@ -327,6 +329,8 @@ def test_general_physics_model_validation(lib):
         assert lib.pwa_set_launch_shape(h, 2, 1, 2) == L.PWA_E_INVALID
         assert lib.pwa_set_launch_shape(h, 3, 1, 2) == L.PWA_OK
         assert lib.pwa_set_launch_shape(h, 3, 3, 2) == L.PWA_E_INVALID   # not built
+        assert lib.pwa_set_launch_shape(h, 3, 4, 3) == L.PWA_OK
+        assert lib.pwa_set_launch_shape(h, 3, 8, 3) == L.PWA_E_INVALID   # not built
         assert lib.pwa_bind_oriented(h, fake, fake, fake, fake, 10, fake, fake, fake, fake, 10,
                                      fake, 1 << 30, None) == L.PWA_E_INVALID
     finally:

@@ -74,6 +74,9 @@ CASES = {
     "spin1_k4": (GModel([0, 1, 2, 0], [0, 1, 2, 2], parent_spin=1), 2501, 10001),
     "spin1_flatte_k5": (GModel([2, 0, 1, 0, 1], [0, 1, 2, 0, 1], lineshape=[1, 0, 0, 0, 0],
                                parent_spin=1), 1999, 8003),
+    # the GPU-scale layout (the automatic 4 x 3 shape of the general path)
+    "spin1_flatte_k12": (GModel(*synth.resonance_layout(12), lineshape=[0, 0, 1] + [0] * 9,
+                                parent_spin=1), 1203, 5001),
 }
 
 
@@ -135,9 +138,9 @@ def test_general_intensity(gcase):
         np.testing.assert_allclose(got, ref, rtol=rtol, atol=0)
 
 
-@pytest.mark.parametrize("groups", [1, 2, 4, 8])
-def test_general_launch_shapes(groups):
-    """Every built shape of the general path (G waves x 2 resonances, one
+@pytest.mark.parametrize("groups,res", [(1, 2), (2, 2), (4, 2), (8, 2), (4, 3)])
+def test_general_launch_shapes(groups, res):
+    """Every built shape of the general path (G waves x R resonances, one
     block per batch of 64 events) gives the oracle's H v."""
     model = GModel([2, 0], [0, 1], lineshape=[1, 0], parent_spin=1)
     th = _theta(model, 71)
@@ -145,9 +148,9 @@ def test_general_launch_shapes(groups):
     v = _rng(74).normal(size=th.size)
     f, g, hv = oracle.hvp(data, mc, model, th, v)
     SH = oracle.hvp_scale(data, mc, model, th, v)
-    say(f"[general shape] G={groups}")
+    say(f"[general shape] G={groups} R={res}")
     lik = _lik(model, data, mc)
-    lik.set_launch_shape(3, groups, 2)
+    lik.set_launch_shape(3, groups, res)
     h, nll, _ = lik.hvp(th, v)
     assert abs(float(nll) - f) <= 1e-10 * abs(f)
     assert_close("hvp", h.cpu().numpy(), hv, SH, 1e-10)
