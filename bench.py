@@ -134,6 +134,51 @@ def cpu_baseline(W, data, mc, n_data=100_000, n_mc=500_000):
             "host_cores_available": len(os.sched_getaffinity(0))}
 
 
+def cpu_baseline_general(n_data=20_000, n_mc=80_000):
+    """The oracle, as it is, on the general physics path's three models
+    (K = 12 layout; a Flatte scalar, a spin-1 parent, both), single thread,
+    one NLL+grad+HVP over a bounded sample of the same kind of events as the
+    GPU section (uniform over phase space and orientation)."""
+    import types
+    import oracle
+    import synth
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    ch, sp = synth.resonance_layout(12)
+    kf = next(k for k in range(len(ch)) if ch[k] == 2 and sp[k] == 0)
+    rng = np.random.Generator(np.random.PCG64(21))
+    ev = []
+    for n in (n_data, n_mc):
+        s12, s13 = synth.uniform_phase_space(n, rng)
+        cb, g = synth.uniform_orientation(n, rng)
+        ev.append((s12, s13, cb, g))
+    th0 = synth.draw_theta(ch, sp, np.random.Generator(np.random.PCG64(12)))
+    v = np.random.Generator(np.random.PCG64(13)).normal(size=4 * len(ch))
+    out = {}
+    for name, flatte, ps in (("flatte", True, 0), ("spin1", False, 1), ("spin1_flatte", True, 1)):
+        model = types.SimpleNamespace(
+            channel=list(ch), spin=list(sp), width_mode=0, parent_mass=synth.PARENT_MASS,
+            masses=synth.DAUGHTER_MASSES, r=synth.R_BARRIER, n_res=len(ch),
+            lineshape=[1 if (flatte and k == kf) else 0 for k in range(len(ch))],
+            flatte_masses=synth.FLATTE_MASSES, flatte_ratio=synth.FLATTE_RATIO, parent_spin=ps)
+        th = th0.copy()
+        if flatte:
+            th[4 * kf + 2:4 * kf + 4] = synth.FLATTE_F0
+        d, m = (ev[0], ev[1]) if ps == 1 else (ev[0][:2], ev[1][:2])
+        t0 = time.perf_counter()
+        oracle.hvp(d, m, model, th, v)
+        dt = time.perf_counter() - t0
+        out[name] = {"value": round((n_data + n_mc) / dt, 1), "unit": "events/s", "cores": 1,
+                     "kind": "oracle", "sample": f"one NLL+grad+HVP over {n_data} data + {n_mc} MC "
+                                                 f"events; {dt:.2f} s"}
+    if limiter is not None:
+        limiter.unregister()
+    return out
+
+
 def _oracle_shard(args):
     import oracle
     d, m, W, theta, v = args
@@ -600,6 +645,8 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(W, data, mc)
         result["cpu_all_cores"] = cpu_all_cores(W, data, mc)
+        if not args.no_general:
+            result["cpu_baseline_general_path"] = cpu_baseline_general()
     print(json.dumps(result), flush=True)
 
 
