@@ -393,6 +393,10 @@ int pwa_create(const pwa_model* m, int32_t streams, pwa_ctx** out) {
   }
   fs.zero_field = gen ? nf++ : -1;
   fs.n_fields = nf;
+  if (nf > (gen ? MAX_GEN_FIELDS : MAX_FIELDS)) {   // bounded by the layout above
+    delete c;
+    return PWA_E_INVALID;
+  }
   ModelDev& md = c->md;
   memset(&md, 0, sizeof(md));
   md.M2 = m->parent_mass * m->parent_mass;

@@ -108,6 +108,9 @@ struct FieldSpec {
 };
 
 constexpr int MAX_FIELDS = 18;   // 3 s + 6 u + 9 g planes at most
+// general path: 3 s + 6 Flatte (g, h) + 9 g + 36 spin-1 u^mu (re, im of
+// mu = +1, -1 per (channel, J)) + 1 zero plane at most
+constexpr int MAX_GEN_FIELDS = 55;
 
 // Stream staging geometry (wave-group layout): one 16-byte load per lane
 // brings 64 events of stage_ppi planes; the LDS stage buffers hold the

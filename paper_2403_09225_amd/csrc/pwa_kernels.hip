@@ -773,6 +773,14 @@ size_t stage_lds_bytes(int n_fields, int bytes) {
   return (size_t)NSTAGE * stage_planes(n_fields, bytes) * 64 * bytes;
 }
 
+// Dynamic LDS of a pass kernel: NSTAGE stage buffers (layout 2), one
+// (layout 3, the general path), none (layout 1).
+size_t pass_lds_bytes(int layout, int n_fields, int bytes) {
+  if (layout == 2) return stage_lds_bytes(n_fields, bytes);
+  if (layout == 3) return (size_t)stage_planes(n_fields, bytes) * 64 * bytes;
+  return 0;
+}
+
 // s_waitcnt immediate (gfx9 field layout) that waits until at most n vector
 // memory operations of this wave are in flight and leaves the other counters
 // alone; and the wave-uniform dispatch of it (immediates only).
@@ -1167,9 +1175,12 @@ __global__ __launch_bounds__(64 * G) void wg_kernel(EvalArgs a) {
 // with gamma u and alpha u replaced by P = sum_mu gamma^mu u^mu and
 // Q = sum_mu alpha^mu u^mu, and g by the complex g + i h, so the finaliser
 // is shared.  Wave-group layout as wg_kernel (G waves x R resonances, z^mu
-// and zdot^mu exchanged through LDS); stream values are loaded straight
-// into registers (this path favours generality over the last factor of
-// speed).
+// and zdot^mu exchanged through LDS, double buffered).  The stream of each
+// batch is staged in LDS with the same 16-byte global-to-LDS loads as
+// wg_kernel, in a single stage buffer (the stream has up to 55 planes here):
+// the loads of batch b + 1 are issued once every wave has read batch b
+// (after the exchange barrier) and are waited for before the barrier that
+// opens batch b + 1, so they fly during the exchange and pass 2.
 // ------------------------------------------------------------------------
 template <typename Real, int MODE, int G, int R>
 __global__ __launch_bounds__(64 * G) void wgx_kernel(EvalArgs a) {
@@ -1189,16 +1200,23 @@ __global__ __launch_bounds__(64 * G) void wgx_kernel(EvalArgs a) {
   const int64_t stride = a.stride;
   const int nmu = a.nmu;
   const Real* tsrc = ((sizeof(Real) == 8) ? (const Real*)a.tbl64 : (const Real*)a.tbl32) + wv * R * TS;
-  __shared__ Real xch[2][G][2][NQ][64][2];
+  constexpr int PPI = stage_ppi((int)sizeof(Real));   // planes per load instruction
+  constexpr int LPP = 64 / PPI;                       // lanes per plane
+  constexpr int JMAX = (stage_planes(MAX_GEN_FIELDS, (int)sizeof(Real)) / PPI + G - 1) / G;
+  extern __shared__ __attribute__((aligned(16))) char stage_lds[];
+  Real* stg = (Real*)stage_lds;   // nfp planes x 64 events (dynamic LDS)
+  // z^mu (, zdot^mu) shares of the G waves; single buffered: the barrier
+  // that opens the next batch follows every wave's reads of this one
+  __shared__ Real xch[G][2][NQ][64][2];
 
-  // plane bases of this wave's resonances: s, g, h, u^0 (re, im), u^1 (re, im)
-  const Real* pb[R][7];
+  // LDS offsets (reals) of this wave's planes: s, g, h, u^0 (re, im), u^1 (re, im)
+  int fo[R][7];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int* it = a.itbl + (wv * R + r) * ITS;
     const int sl[7] = {IT_S, IT_G, IT_H, IT_U, IT_UI, IT_U1R, IT_U1I};
 #pragma unroll
-    for (int f = 0; f < 7; ++f) pb[r][f] = planes + (int64_t)it[sl[f]] * stride;
+    for (int f = 0; f < 7; ++f) fo[r][f] = it[sl[f]] * 64;
   }
 
   double accS = 0.0;
@@ -1206,20 +1224,63 @@ __global__ __launch_bounds__(64 * G) void wgx_kernel(EvalArgs a) {
 #pragma unroll
   for (int j = 0; j < NA; ++j) acc[j] = 0.0;
 
-  int buf = 0;
-  for (int64_t e0 = rg.begin; e0 < rg.end; e0 += 64, buf ^= 1) {
+  const int nbat = (int)((rg.end - rg.begin + 63) / 64);
+  const int nf = a.n_fields;
+  const int ni = (nf + PPI - 1) / PPI;        // load instructions per batch
+  // this wave's load instructions j = wv + G jj (the layout of wg_kernel:
+  // lane l brings 16 bytes of plane j PPI + l / LPP at event (l % LPP) PPI;
+  // in the last group, lanes past the last plane reload that plane into
+  // padding slots that are never read)
+  const uint32_t pbytes = (uint32_t)(stride * (int64_t)sizeof(Real));
+  const uint32_t voff = (uint32_t)(lane / LPP) * pbytes + (uint32_t)(lane % LPP) * 16u;
+  const uint32_t voff_last = (uint32_t)min(lane / LPP, nf - 1 - (ni - 1) * PPI) * pbytes +
+                             (uint32_t)(lane % LPP) * 16u;
+  const Real* bsrc = planes + rg.base + rg.begin;
+  auto issue = [&](int b) {
+    const int64_t off = (int64_t)b * 64;
+#pragma unroll
+    for (int jj = 0; jj < JMAX; ++jj) {
+      const int j = wv + G * jj;
+      if (j < ni) {
+        const char* base = (const char*)(bsrc + (int64_t)j * PPI * stride + off);
+        __builtin_amdgcn_global_load_lds((glob_void_t*)(base + (j == ni - 1 ? voff_last : voff)),
+                                         (lds_void_t*)(stg + j * PPI * 64), 16, 0, 0);
+      }
+    }
+  };
+  if (nbat > 0) issue(0);
+
+  for (int b = 0; b < nbat; ++b) {
+    // batch b is in LDS: this wave's loads (vmcnt), then every wave's
+    wait_vm_at_most(0);
+    lds_barrier();
+    const int64_t e0 = rg.begin + (int64_t)b * 64;
     const bool valid = e0 + lane < rg.end;
-    const int64_t ev = rg.base + (valid ? e0 + lane : rg.begin);
     CReal* tb = opaque_s((CReal*)tsrc);
+    // ---- stream values of this wave's resonances; lanes past the range
+    // (last batch only) hold the padding between the data and MC sets: give
+    // them finite values, their contributions are zeroed below
+    Real sv_[R], g_[R], h_[R], ur_[R][2], ui_[R][2];
+    {
+      const Real* sb = stg + lane;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sv_[r] = valid ? sb[fo[r][0]] : Real(0);
+        g_[r] = valid ? sb[fo[r][1]] : Real(0);
+        h_[r] = valid ? sb[fo[r][2]] : Real(0);
+        ur_[r][0] = valid ? sb[fo[r][3]] : Real(0);
+        ui_[r][0] = valid ? sb[fo[r][4]] : Real(0);
+        ur_[r][1] = (valid && nmu > 1) ? sb[fo[r][5]] : Real(0);
+        ui_[r][1] = (valid && nmu > 1) ? sb[fo[r][6]] : Real(0);
+      }
+    }
     // ---- pass 1: w, u^mu of each resonance; this wave's share of z^mu, zdot^mu
-    Real wr_[R], wi_[R], g_[R], h_[R], ur_[R][2], ui_[R][2];
+    Real wr_[R], wi_[R];
     Real zr[2] = {0, 0}, zi[2] = {0, 0}, zdr[2] = {0, 0}, zdi[2] = {0, 0};
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       CReal* t = tb + r * TS;
-      const Real sv = pb[r][0][ev];
-      g_[r] = pb[r][1][ev];
-      h_[r] = pb[r][2][ev];
+      const Real sv = sv_[r];
       const Real Dr = t[TB_M2] - sv - t[TB_NGE] * h_[r];
       const Real Di = t[TB_NGE] * g_[r];
       const Real inv = rcp_r(Dr * Dr + Di * Di);
@@ -1231,10 +1292,9 @@ __global__ __launch_bounds__(64 * G) void wgx_kernel(EvalArgs a) {
 #pragma unroll
       for (int mu = 0; mu < 2; ++mu) {
         if (mu >= nmu) break;
-        const Real urr = mu == 0 ? mad_nc(pb[r][3][ev], t[TB_UMUL], t[TB_UADD]) : pb[r][5][ev];
-        const Real uii = mu == 0 ? pb[r][4][ev] : pb[r][6][ev];
+        const Real urr = mu == 0 ? mad_nc(ur_[r][0], t[TB_UMUL], t[TB_UADD]) : ur_[r][1];
+        const Real uii = ui_[r][mu];
         ur_[r][mu] = urr;
-        ui_[r][mu] = uii;
         const Real Ur = urr * wr_[r] - uii * wi_[r], Ui = urr * wi_[r] + uii * wr_[r];
         zr[mu] += t[TB_CBR] * Ur - t[TB_CBI] * Ui;
         zi[mu] += t[TB_CBR] * Ui + t[TB_CBI] * Ur;
@@ -1250,25 +1310,30 @@ __global__ __launch_bounds__(64 * G) void wgx_kernel(EvalArgs a) {
 #pragma unroll
       for (int mu = 0; mu < 2; ++mu) {
         if (mu >= nmu) break;
-        xch[buf][wv][mu][0][lane][0] = zr[mu];
-        xch[buf][wv][mu][0][lane][1] = zi[mu];
+        xch[wv][mu][0][lane][0] = zr[mu];
+        xch[wv][mu][0][lane][1] = zi[mu];
         if constexpr (ZD) {
-          xch[buf][wv][mu][NQ - 1][lane][0] = zdr[mu];
-          xch[buf][wv][mu][NQ - 1][lane][1] = zdi[mu];
+          xch[wv][mu][NQ - 1][lane][0] = zdr[mu];
+          xch[wv][mu][NQ - 1][lane][1] = zdi[mu];
         }
       }
-      __syncthreads();
+    }
+    // every wave has read batch b's stream values (its LDS reads drained at
+    // the barrier): refill the stage buffer with batch b + 1
+    lds_barrier();
+    if (b + 1 < nbat) issue(b + 1);
+    if constexpr (G > 1) {
 #pragma unroll
       for (int mu = 0; mu < 2; ++mu) {
         if (mu >= nmu) break;
         zr[mu] = zi[mu] = zdr[mu] = zdi[mu] = 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          zr[mu] += xch[buf][g][mu][0][lane][0];
-          zi[mu] += xch[buf][g][mu][0][lane][1];
+          zr[mu] += xch[g][mu][0][lane][0];
+          zi[mu] += xch[g][mu][0][lane][1];
           if constexpr (ZD) {
-            zdr[mu] += xch[buf][g][mu][NQ - 1][lane][0];
-            zdi[mu] += xch[buf][g][mu][NQ - 1][lane][1];
+            zdr[mu] += xch[g][mu][NQ - 1][lane][0];
+            zdi[mu] += xch[g][mu][NQ - 1][lane][1];
           }
         }
       }
@@ -1832,7 +1897,8 @@ hipError_t launch_eval(int is_f32, int mode, int layout, int T, int R, const Eva
                        int nblocks, hipStream_t st) {
   EvalFn fn = pick_fn(is_f32, mode, layout, T, R);
   if (!fn) return hipErrorInvalidValue;
-  const size_t lds = layout == 2 ? stage_lds_bytes(a.n_fields, is_f32 ? 4 : 8) : 0;
+  if (layout == 3 && a.n_fields > MAX_GEN_FIELDS) return hipErrorInvalidValue;
+  const size_t lds = pass_lds_bytes(layout, a.n_fields, is_f32 ? 4 : 8);
   hipLaunchKernelGGL(fn, dim3(nblocks), dim3(layout >= 2 ? 64 * T : BLOCK), lds, st, a);
   return hipGetLastError();
 }
@@ -1841,7 +1907,7 @@ int eval_occupancy(int is_f32, int mode, int layout, int T, int R, int n_fields)
   EvalFn fn = pick_fn(is_f32, mode, layout, T, R);
   if (!fn) return 0;
   int nb = 0;
-  const size_t lds = layout == 2 ? stage_lds_bytes(n_fields, is_f32 ? 4 : 8) : 0;
+  const size_t lds = pass_lds_bytes(layout, n_fields, is_f32 ? 4 : 8);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fn, layout >= 2 ? 64 * T : BLOCK,
                                                    lds) != hipSuccess)
     return 0;
