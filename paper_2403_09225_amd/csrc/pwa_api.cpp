@@ -142,7 +142,7 @@ void auto_shape(int K, int& L, int& T, int& R) {
 // General physics path (layout 3): G waves of 2 resonances, or 4 waves of 3
 // for 8 < K <= 12 (no padded slots and half the waves repeating the
 // per-event head: at K = 12, 1M + 5M events, the FP64 H v pass with a
-// Flatte resonance takes 0.82 against 1.10 ms at 8 x 2, 1.21 against 1.43 ms
+// Flatte resonance takes 0.55 against 0.73 ms at 8 x 2, 0.75 against 0.98 ms
 // for a spin-1 parent).
 void auto_gen_shape(int K, int& L, int& T, int& R) {
   L = 3;
