@@ -74,3 +74,27 @@ def test_threaded_training_set_matches_single_stream_workers():
     assert np.array_equal(ids, np.concatenate(idss))
     assert torch.equal(x, torch.cat(xs))
     assert torch.allclose(y, torch.cat(ys), rtol=0, atol=1e-4)
+
+
+def test_threaded_evaluation_matches_single_stream_workers():
+    """parallel_evaluate gives, toy by toy, the rows each worker's toy stream
+    gives alone (iterations and success flags; wall times differ), and its
+    summary is the one of those rows."""
+    from paper_2403_09225_amd.learned_start import (ToyStudy, load_proposal, parallel_evaluate,
+                                                    resonance_layout, summarize)
+    net, prior, blind, meta = load_proposal()
+    ch, sp = resonance_layout(int(meta["K"]))
+    base = ToyStudy(ch, sp, 50_000, prior=prior, seed=6)
+    say("[learned start] threaded evaluation, 2 workers x 2 toys")
+    summary, rows = parallel_evaluate(ch, sp, prior, base.mc, net, 4, 5_000, 2, 2, seed=8,
+                                      blind=blind)
+    ref = []
+    for w in range(2):
+        st = ToyStudy(ch, sp, 0, prior=prior, seed=8 * 1000 + w, mc=base.mc)
+        ref += st.evaluate_rows(net, 2, 5_000, 2, blind=blind)
+    keys = ("proposal_success", "blind_success", "random_success_fraction", "proposal_iterations",
+            "blind_iterations", "random_iterations")
+    assert len(rows) == len(ref) == 4
+    for r, q in zip(rows, ref):
+        assert all(r[k] == q[k] for k in keys), (r, q)
+    assert summary["proposal_success_rate"] == summarize(ref, 5_000, 2, 0.01)["proposal_success_rate"]
