@@ -224,7 +224,9 @@ def fit_compare(lik, W, cap_s=60.0, n_starts=5):
     """Newton-CG time to minimum from seeded starts near the generating
     parameters, with FP64 HVPs and with FP32 HVPs inside CG (line search and
     convergence test in FP64 in both), for scipy's forcing term (the paper's
-    fits) and for the relative one, and with CG preconditioned by |H|^-1.
+    fits) and for the relative one, each with plain and with reconjugated CG
+    (every direction H-conjugated to the earlier ones of its solve), and
+    with CG preconditioned by |H|^-1.
     Per variant: the first start in detail, and the totals over n_starts
     starts."""
     import synth
@@ -232,13 +234,13 @@ def fit_compare(lik, W, cap_s=60.0, n_starts=5):
     starts = [W.theta_true + rng.normal(scale=np.tile([0.02, 0.02, 0.002, 0.002], W.n_res))
               for _ in range(n_starts)]
     out = {}
-    for forcing in ("relative", "scipy"):
+    for forcing, rc in (("relative", False), ("scipy", False), ("relative", True), ("scipy", True)):
         rec = {}
         for prec in ("f64", "f32"):
             runs = []
             for i, start in enumerate(starts):
                 th, rep = lik.fit(start, xtol=1e-8, maxiter=200, time_cap_s=cap_s,
-                                  hvp_precision=prec, forcing=forcing)
+                                  hvp_precision=prec, forcing=forcing, reconjugate=rc)
                 runs.append(rep)
             r0 = runs[0]
             rec[prec] = {"seconds": round(r0["seconds"], 4), "nll": r0["nll"],
@@ -252,7 +254,7 @@ def fit_compare(lik, W, cap_s=60.0, n_starts=5):
         key = f"seconds_total_{n_starts}_starts"
         rec[f"speedup_mixed_vs_fp64_{n_starts}_starts"] = round(rec["f64"][key] / max(rec["f32"][key], 1e-9), 3)
         rec["nll_diff_mixed_minus_fp64"] = rec["f32"]["nll"] - rec["f64"]["nll"]
-        out[f"forcing_{forcing}"] = rec
+        out[f"forcing_{forcing}" + ("_reconjugated" if rc else "")] = rec
     # CG preconditioned with |H|^-1 (relative forcing), FP64 and FP32 HVPs
     for prec in ("f64", "f32"):
         runs = [lik.fit(start, xtol=1e-8, maxiter=200, time_cap_s=cap_s, forcing="relative",

@@ -287,6 +287,14 @@ typedef struct pwa_fit_opts {
                              largest), rebuilt when a solve needs more than
                              max(8, P/4) CG steps; those HVPs are counted
                              in n_hvp                                     */
+  int32_t reconjugate;    /* 0: CG's three-term recurrence only; 1: each new
+                             search direction is also made H-conjugate to
+                             every earlier one of the same solve (Gram-Schmidt
+                             with the stored H p_j: no extra HVPs), with the
+                             exact line minimum -(r.p)/(p.Hp) as step.  The
+                             recurrence loses conjugacy on an ill-conditioned
+                             H, so that plain CG can take several times P
+                             steps; with FP32 HVPs more so                */
 } pwa_fit_opts;
 
 /* Fit report (host memory, written by pwa_fit). */

@@ -44,7 +44,7 @@ class PwaFitOpts(ctypes.Structure):
     _fields_ = [("xtol", c_double), ("maxiter", c_int32), ("cg_maxiter", c_int32),
                 ("time_cap_s", c_double), ("hvp_precision", c_int32),
                 ("free_mask_set", c_int32), ("free_mask", ctypes.c_uint8 * (4 * PWA_MAX_RES)),
-                ("forcing", c_int32), ("precondition", c_int32)]
+                ("forcing", c_int32), ("precondition", c_int32), ("reconjugate", c_int32)]
 
 
 class PwaMlpDims(ctypes.Structure):

@@ -304,12 +304,13 @@ class Likelihood:
     # ------------------------------------------------------------------- fit
     def fit(self, theta0, xtol=1e-8, maxiter=200, cg_maxiter=0, time_cap_s=0.0,
             hvp_precision="f64", free_mask=None, forcing="scipy", precondition=False,
-            method="newton-cg"):
+            method="newton-cg", reconjugate=False):
         """Newton-CG fit from theta0 (method="bfgs": the gradient-only BFGS
         comparator, pwa_fit_bfgs); returns (theta, report dict).
         forcing: "scipy" (eta = min(1/2, sqrt(sum|g|))) or "relative"
         (eta = min(1/2, sqrt(sum|g| / sum|g_0|))).  precondition: CG with
-        the inverse of |H| built from HVPs (see pwa_fit_opts)."""
+        the inverse of |H| built from HVPs; reconjugate: CG directions kept
+        H-conjugate to all earlier ones of a solve (see pwa_fit_opts)."""
         entry = {"newton-cg": self.lib.pwa_fit, "bfgs": self.lib.pwa_fit_bfgs}[method]
         t = self._theta(theta0).clone()
         o = L.PwaFitOpts()
@@ -320,6 +321,7 @@ class Likelihood:
         o.hvp_precision = L.PWA_PREC_F32 if hvp_precision == "f32" else L.PWA_PREC_F64
         o.forcing = {"scipy": 0, "relative": 1}[forcing]
         o.precondition = 1 if precondition else 0
+        o.reconjugate = 1 if reconjugate else 0
         o.free_mask_set = 0 if free_mask is None else 1
         if free_mask is not None:
             for i, f in enumerate(free_mask):

@@ -964,6 +964,7 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
   if (!(o->xtol > 0.0) || !isfinite(o->xtol)) return PWA_E_INVALID;
   if (o->forcing != 0 && o->forcing != 1) return PWA_E_INVALID;
   if (o->precondition != 0 && o->precondition != 1) return PWA_E_INVALID;
+  if (o->reconjugate != 0 && o->reconjugate != 1) return PWA_E_INVALID;
   const int hp = o->hvp_precision;
   if (check_prec(c, hp) != PWA_OK) return PWA_E_INVALID;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1029,8 +1030,17 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
     for (int i = 0; i < P; ++i) pcg[i] = -zc[i];
     double dri0 = dot(r, zc);
     int i = 0;
+    // earlier directions of this solve, their H p and p.Hp (reconjugate)
+    std::vector<std::vector<double>> dirs, hdirs;
+    std::vector<double> dcurv;
     for (int k = 0; k < cg_max; ++k) {
       if (sum_abs(r) <= termcond) break;
+      if (o->reconjugate == 1) {
+        for (size_t j = 0; j < dirs.size(); ++j) {
+          const double cj = dot(pcg, hdirs[j]) / dcurv[j];
+          for (int q = 0; q < P; ++q) pcg[q] -= cj * dirs[j][q];
+        }
+      }
       if (!F.hvp(x, pcg, Ap)) return F.err;
       const double curv = dot(pcg, Ap);
       if (0.0 <= curv && curv <= 3.0 * 2.220446049250313e-16) break;
@@ -1040,7 +1050,14 @@ int pwa_fit(pwa_ctx* c, double* d_theta, const pwa_fit_opts* o, pwa_fit_report* 
         for (int j = 0; j < P; ++j) xs[j] = dri0 / (-curv) * pcg[j];
         break;
       }
-      const double al = dri0 / curv;
+      // step to the minimum along pcg: (r.z) / (p.Hp) for the recurrence's
+      // direction, -(r.p) / (p.Hp) in general
+      const double al = o->reconjugate == 1 ? -dot(r, pcg) / curv : dri0 / curv;
+      if (o->reconjugate == 1) {
+        dirs.push_back(pcg);
+        hdirs.push_back(Ap);
+        dcurv.push_back(curv);
+      }
       for (int j = 0; j < P; ++j) {
         xs[j] += al * pcg[j];
         r[j] += al * Ap[j];

@@ -144,6 +144,9 @@ def test_unbound_and_bad_bind_arguments(lib):
         opts = L.PwaFitOpts()
         opts.xtol = 1e-8
         assert lib.pwa_fit(h, fake, ctypes.byref(opts), None, st) == L.PWA_E_STATE
+        opts.reconjugate = 2
+        assert lib.pwa_fit(h, fake, ctypes.byref(opts), None, st) in (L.PWA_E_STATE, L.PWA_E_INVALID)
+        opts.reconjugate = 0
         assert lib.pwa_fit(h, fake, None, None, st) == L.PWA_E_INVALID
         assert lib.pwa_fit_bfgs(h, fake, ctypes.byref(opts), None, st) == L.PWA_E_STATE
         assert lib.pwa_fit_bfgs(h, fake, None, None, st) == L.PWA_E_INVALID
