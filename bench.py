@@ -320,7 +320,7 @@ def k30_bench(steps=20):
     return out
 
 
-def general_bench(reps=20):
+def general_bench(reps=20, models=("flatte", "spin1", "spin1_flatte")):
     """The general physics path on the GPU-scale layout (K = 12, 1M data +
     5M MC events, uniform over phase space and parent orientation, FP64
     stream): a Flatte f0(980)-like scalar in the (23) channel (Sec. 3's
@@ -347,6 +347,8 @@ def general_bench(reps=20):
     out = {"workload": f"K=12, {nd} data + {nm} MC events (uniform), FP64 stream; Flatte "
                        f"resonance {kf} (channel (23), J = 0)"}
     for name, lshape, ps in (("flatte", ls, 0), ("spin1", None, 1), ("spin1_flatte", ls, 1)):
+        if name not in models:
+            continue
         lik = Likelihood(ch, sp, lineshape=lshape, flatte_masses=synth.FLATTE_MASSES,
                          flatte_ratio=synth.FLATTE_RATIO, parent_spin=ps)
         if ps == 1:
@@ -501,6 +503,9 @@ def main():
     ap.add_argument("--no-k30", action="store_true", help="skip the K = 30, 24M-event section")
     ap.add_argument("--no-general", action="store_true",
                     help="skip the general physics path section (Flatte, spin-1 parent)")
+    ap.add_argument("--general-model", default="all",
+                    choices=["all", "flatte", "spin1", "spin1_flatte"],
+                    help="run the general physics path section for one model only")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -641,7 +646,9 @@ def main():
         torch.cuda.empty_cache()
         print("[bench] K = 30 workload done", file=sys.stderr, flush=True)
     if not args.no_general:
-        result["general_physics_path"] = general_bench()
+        result["general_physics_path"] = general_bench(
+            models=("flatte", "spin1", "spin1_flatte") if args.general_model == "all"
+            else (args.general_model,))
         torch.cuda.empty_cache()
         print("[bench] general physics path done", file=sys.stderr, flush=True)
     if not args.no_cpu:
