@@ -121,11 +121,15 @@ bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 // waves per SIMD) for 16 < K <= 32.  A 12-wave block would hold 3 waves per
 // SIMD, which caps a wave at 168 VGPRs: the FP64 H v build of 12 x 2 then
 // spills and runs 4x slower than 8 x 3 (2.47 against 0.59 ms at K = 20,
-// 6M events).  Layout 1 (T lanes of a wave share an event) serves K > 32.
-// For the NLL alone layout 2 also beats one lane per event with all
-// resonances (layout 1, T = 1): 157 against 191 us at K = 12, 222 against
-// 426 us at K = 30 (6M events, FP64).
-void auto_shape(int K, int& L, int& T, int& R) {
+// 6M events).  For the NLL alone layout 2 also beats one lane per event with
+// all resonances (layout 1, T = 1): 157 against 191 us at K = 12, 222 against
+// 426 us at K = 30 (6M events, FP64).  Above K = 32 the passes without the
+// full H v moments take 8 waves of 8 resonances (K = 40 and 64, 6M events,
+// FP64: NLL 1.37 -> 0.36 ms, NLL + grad 1.42 -> 0.63 ms, direction-only H v
+// 2.27 -> 0.89 ms against layout 1); the full H v pass, whose 18 moments per
+// resonance do not fit 8 of them per lane, stays in layout 1 (T lanes of a
+// wave share an event, 32 x 2).
+void auto_shape(int K, int mode, int& L, int& T, int& R) {
   L = 2;
   if (K <= 2) { T = 1; R = 2; return; }
   if (K <= 4) { T = 1; R = 4; return; }
@@ -135,6 +139,7 @@ void auto_shape(int K, int& L, int& T, int& R) {
   if (K <= 16) { T = 8; R = 2; return; }
   if (K <= 24) { T = 8; R = 3; return; }
   if (K <= 32) { T = 8; R = 4; return; }
+  if (mode != MODE_HVP) { T = 8; R = 8; return; }
   L = 1;
   T = 32; R = 2;
 }
@@ -170,7 +175,7 @@ void shape_of(const pwa_ctx* c, int mode, int& L, int& T, int& R) {
     T = c->shape_T;
     R = c->shape_R;
   } else {
-    auto_shape(c->K, L, T, R);
+    auto_shape(c->K, mode, L, T, R);
   }
 }
 

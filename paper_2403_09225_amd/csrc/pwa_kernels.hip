@@ -1788,7 +1788,7 @@ hipError_t launch_table(const double* theta, const double* v, const ModelDev& md
   X(1, 2) X(1, 4) X(2, 4) X(4, 2) X(4, 3) X(4, 4) X(8, 2) X(8, 4) X(16, 2) X(16, 4) X(32, 2)
 
 // Wave-group shapes (waves per block G, resonances per wave R).
-#define PWA_WG_SHAPES(X) X(1, 2) X(1, 4) X(2, 3) X(2, 4) X(3, 4) X(4, 2) X(4, 3) X(5, 3) X(6, 2) X(8, 2) X(8, 3) X(8, 4) X(12, 2)
+#define PWA_WG_SHAPES(X) X(1, 2) X(1, 4) X(2, 3) X(2, 4) X(3, 4) X(4, 2) X(4, 3) X(5, 3) X(6, 2) X(8, 2) X(8, 3) X(8, 4) X(12, 2) X(8, 8)
 
 bool wg_shape_built(int G, int R) {
 #define PWA_IS(GG, RR) if (G == GG && R == RR) return true;

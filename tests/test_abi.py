@@ -99,6 +99,7 @@ def test_valid_context_host_queries(lib):
         assert lib.pwa_set_launch_shape(h, 1, 4, 3) == L.PWA_OK
         assert lib.pwa_set_launch_shape(h, 2, 4, 3) == L.PWA_OK
         assert lib.pwa_set_launch_shape(h, 2, 7, 3) == L.PWA_E_INVALID   # not built
+        assert lib.pwa_set_launch_shape(h, 2, 8, 8) == L.PWA_OK
         assert lib.pwa_set_launch_shape(h, 0, 0, 0) == L.PWA_OK
     finally:
         lib.pwa_destroy(h)

@@ -54,7 +54,7 @@ def test_fp64_parity(K, nd, nm, seed, wm):
 
 @pytest.mark.parametrize("shape", [(1, 4, 3), (1, 4, 4), (1, 8, 2), (1, 8, 4), (1, 16, 2),
                                    (1, 16, 4), (1, 32, 2), (2, 4, 3), (2, 3, 4), (2, 6, 2),
-                                   (2, 8, 2), (2, 8, 3), (2, 8, 4), (2, 12, 2)])
+                                   (2, 8, 2), (2, 8, 3), (2, 8, 4), (2, 12, 2), (2, 8, 8)])
 def test_every_launch_shape(shape):
     say(f"[shape] K=12 layout,groups,R={shape}")
     model, th, data, mc, v = case(12, 1777, 6001, 20)
@@ -68,7 +68,8 @@ def test_every_launch_shape(shape):
                                      (64, (1, 32, 2)), (2, (2, 1, 2)), (3, (2, 1, 4)), (5, (2, 2, 3)),
                                      (7, (2, 2, 4)), (8, (2, 4, 2)), (16, (2, 8, 2)), (22, (2, 8, 3)),
                                      (15, (2, 5, 3)), (24, (2, 12, 2)), (12, (2, 3, 4)),
-                                     (30, (2, 8, 4)), (25, (2, 8, 4))])
+                                     (30, (2, 8, 4)), (25, (2, 8, 4)), (40, (2, 8, 8)),
+                                     (64, (2, 8, 8))])
 def test_small_k_shapes(K, shape):
     say(f"[shape] K={K} layout,groups,R={shape}")
     model, th, data, mc, v = case(K, 913, 3007, 21 + K)
@@ -267,7 +268,8 @@ def test_hvp_reuse_parity(K, nd, nm, seed, shape):
     """pwa_hvp_reuse (direction moments only, theta-only totals of the last
     pwa_hvp) against the oracle for several new directions, FP64 and FP32
     streams, and equal to a full pass to rounding, in both layouts (team
-    layout: K > 32 and the (1, 16, 2) case)."""
+    layout: the (1, 16, 2) case and the full pass at K > 32, whose
+    direction-only pass runs in 8 waves x 8)."""
     say(f"[hvp reuse] K={K} shape={shape}")
     model, th, data, mc, v = case(K, nd, nm, seed)
     lik = likelihood(model, data, mc, streams=("f64", "f32"))
@@ -291,7 +293,12 @@ def test_hvp_reuse_parity(K, nd, nm, seed, shape):
             assert_close(f"hv reuse {prec} dir {d}", _np(hv), hvo, SHw, tol)
             full, _, _ = lik.hvp(th, w)
             scale = SHw
-            assert np.all(np.abs(_np(hv) - _np(full)) <= (1e-12 if prec == "f64" else 1e-6) * scale)
+            # above K = 32 the automatic shapes differ (the full pass in the
+            # team layout, the direction-only pass in 8 waves x 8): their FP32
+            # sums take other rounding orders, and agree to the FP32 stream's
+            # bound, not to one order's last bits
+            b32 = 1e-6 if (shape is not None or K <= 32) else tol32
+            assert np.all(np.abs(_np(hv) - _np(full)) <= (1e-12 if prec == "f64" else b32) * scale)
 
 
 def test_hvp_reuse_state():
